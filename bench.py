@@ -1,0 +1,184 @@
+"""Benchmark: exact sieve of Eratosthenes on one MI355X.
+
+Default workload: the count-only sieve of [2, 1e10) (pi = 455052511), one
+step = one sieve_range_count call (base primes resident, pre-sieve, dense and
+sparse marking, popcount reduction, 8-byte readback).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
+
+Throughput is sieved integers per second, (hi - lo) / step time.  The roofline
+object prices the marking kernel's algorithmic LDS work (one 32-bit LDS
+atomic per crossed-off odd multiple of every base prime 7 <= p <= sqrt(hi-1),
+plus one LDS write and one read per bitmap word) against the chip's LDS
+lane-op peak; see the design doc for the derivation.  The cpu_baseline object
+times the CPU oracle on the host over the same range.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sieved ints/s on [2,1e10] (% roofline); batched vs plain speedup; p50/p99 ms"
+
+WORKLOADS = {
+    "c1": dict(lo=2, hi=10**7, bitmap=True, pi=664579,
+               name="plain sieve of [2, 1e7): odd-only bitmap to HBM plus pi"),
+    "c2": dict(lo=2, hi=10**9, bitmap=True, pi=50847534,
+               name="plain sieve of [2, 1e9): odd-only bitmap (62.5 MB) to HBM plus pi"),
+    "c3": dict(lo=2, hi=10**10, bitmap=False, pi=455052511,
+               name="count-only segmented sieve of [2, 1e10)"),
+}
+
+# MI355X: 256 CUs at 2.4 GHz; 32 LDS banks of 4 bytes per CU, one 32-bit
+# lane access per bank per clock.
+N_CU, CLOCK_HZ, LDS_LANES_PER_CLK = 256, 2.4e9, 32
+LDS_PEAK_LANE_OPS = N_CU * CLOCK_HZ * LDS_LANES_PER_CLK
+HBM_PEAK_BPS = 8.0e12
+
+
+def algorithmic_lds_ops(primes, lo, hi):
+    """Marks (odd multiples m of each base prime 7 <= p <= isqrt(hi-1) with
+    max(p^2, lo) <= m < hi) plus two LDS accesses per bitmap word."""
+    import numpy as np
+
+    p = primes[(primes >= 7)].astype(np.int64)
+    p = p[p * p <= hi - 1]
+    a = np.maximum(p * p, lo)
+    jhi = (hi - 1) // p          # largest multiplier with m < hi
+    jlo = -(-a // p)             # smallest multiplier with m >= a
+    odd_upto = lambda x: (x + 1) // 2  # odd j in [1, x]
+    marks = int(np.maximum(odd_upto(jhi) - odd_upto(jlo - 1), 0).sum())
+    words = (hi // 2 - lo // 2 + 31) // 32
+    return marks, marks + 2 * words, words
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["sieve_kernels.hip", "sieve_internal.h"]:
+        with open(os.path.join(ROOT, "paper_1205_4883_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(lo, hi, expect_pi):
+    import oracle  # CPU-baseline leg only
+
+    oracle.build(force=False)
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    pi = oracle.count(lo, hi, threads=threads)
+    dt = time.perf_counter() - t0
+    assert pi == expect_pi, (pi, expect_pi)
+    return {"value": (hi - lo) / dt, "unit": "ints/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole workload: oracle count of [{lo}, {hi}) on {threads} threads, "
+                      f"{dt:.2f} s, pi={pi}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "split of a range is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1205_4883_amd as sv
+
+    wl = WORKLOADS[args.workload]
+    lo, hi = wl["lo"], wl["hi"]
+    s = sv.Sieve(0)
+    stream = torch.cuda.current_stream(0)
+    out = s.alloc_words(lo, hi) if wl["bitmap"] else None
+
+    def step():
+        if out is None:
+            return sv.sieve_range_count(s.ctx, lo, hi, stream=stream)
+        return sv.sieve_range_bitmap(s.ctx, lo, hi, out, out.numel(), True, stream=stream)
+
+    for _ in range(args.warmup):
+        assert step() == wl["pi"]
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pi = step()
+        kernel_ms.append(sv.sieve_last_kernel_ms(s.ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert pi == wl["pi"], pi
+    ms_per_step = 1e3 * dt / args.steps
+    value = (hi - lo) / (dt / args.steps)
+
+    primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(hi)) + 1)
+    marks, lane_ops, words = algorithmic_lds_ops(primes, lo, hi)
+    k_ms = float(np.mean(kernel_ms))
+    achieved = lane_ops / (k_ms * 1e-3)
+    plan = sv.sieve_plan(lo, hi)
+    roof = {
+        "bound": "lds",
+        "achieved": achieved / 1e9,
+        "peak": LDS_PEAK_LANE_OPS / 1e9,
+        "unit": "Glane-op/s",
+        "frac": achieved / LDS_PEAK_LANE_OPS,
+        "traffic": load_traffic(args.workload),
+        "kernel": "range_kernel<write=%s>" % ("true" if wl["bitmap"] else "false"),
+        "kernel_ms": k_ms,
+        "kernel_ms_min": float(np.min(kernel_ms)),
+        "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": words},
+    }
+    if wl["bitmap"]:
+        roof["hbm_write_GBps"] = 4 * words / (k_ms * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "lo": lo, "hi": hi, "pi": pi,
+                   "presieve_primes": [3, 5, 7, 11, 13, 17, 19, 23, 29, 31],
+                   "seg_bits": plan["seg_bits"], "dense_limit": plan["dense_limit"],
+                   "block_threads": plan["block_threads"], "n_segments": plan["n_segments"]},
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"])
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

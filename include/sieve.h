@@ -1,0 +1,197 @@
+/*
+ * sieve.h - C ABI of the MI355X (gfx950) exact range sieve of Eratosthenes.
+ *
+ * The library finds the primes in a half-open integer range [lo, hi) and
+ * counts them.  This is the problem the paper states: the sieve of
+ * Eratosthenes finds every prime up to a limit by crossing off the multiples
+ * of each prime (Section 1; Section 3.1), and pi(x) counts the primes up to x
+ * (Section 1).  The paper splits n integers into ceil(n/k) blocks that
+ * workers sieve independently (Section 3.1, Eq. 3); here the blocks are
+ * LDS-sized segments that GPU workgroups sieve independently.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status: every call returns a sieve_status (0 = success, negative = error)
+ *   and never throws.  On error the outputs are left untouched, except
+ *   *n_out on SIEVE_EBUFSZ (set to the size needed).  Arguments are checked
+ *   before any device work starts.
+ * Domain: 0 <= lo <= hi <= SIEVE_MAX_HI.  lo == hi is valid (an empty range:
+ *   pi = 0, zero bitmap words).
+ * Bitmap layout: bit i stands for the odd integer (lo & ~1) + 2*i + 1, for
+ *   0 <= i < hi/2 - lo/2 (integer division).  Bits are packed least
+ *   significant first into little-endian uint32 words: bit i is bit (i % 32)
+ *   of word i / 32.  1 means prime.  Bits past the end of the range in the
+ *   last word are 0.  The even prime 2 has no bit but is counted in pi when
+ *   lo <= 2 < hi.
+ * Device buffers: pointers named d_* are device (HBM) addresses on the
+ *   context's device, for example the data_ptr() of a torch tensor.  The
+ *   caller owns them; the library never frees them.
+ * Streams: a `stream` argument is a hipStream_t on the context's device, or
+ *   NULL for the context's own stream.  Work is ordered on that stream.
+ * Threads: a context is used by one host thread at a time.
+ */
+#ifndef SIEVE_H
+#define SIEVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef SIEVE_API
+#define SIEVE_API __attribute__((visibility("default")))
+#endif
+
+typedef enum sieve_status {
+    SIEVE_OK = 0,
+    SIEVE_EINVAL = -1,    /* NULL where a pointer is required, lo > hi, bad tuning */
+    SIEVE_ERANGE = -2,    /* hi > SIEVE_MAX_HI */
+    SIEVE_ENOMEM = -3,    /* device or host allocation failed, or over the HBM budget */
+    SIEVE_EBUFSZ = -4,    /* output buffer too small; *n_out holds the size needed */
+    SIEVE_EDEVICE = -5,   /* a HIP call failed; see sieve_last_hip_error() */
+    SIEVE_ENODEV = -6,    /* no usable gfx950 device */
+    SIEVE_EOVERFLOW = -7  /* a bucket pool overflowed and the retry failed */
+} sieve_status;
+
+/* Largest accepted hi: 10^15.  sqrt(10^15) < 2^25, so base primes fit in 25
+ * bits and every product the kernels form fits in 64 bits. */
+#define SIEVE_MAX_HI 1000000000000000ULL
+
+/* Opaque context: owns the device-resident base-prime table, per-call
+ * counters, batch work queues and the context stream. */
+typedef struct sieve_ctx sieve_ctx;
+
+/* Tuning knobs.  A zero field means "choose automatically".
+ *   seg_bits      odd integers per LDS segment (a multiple of 4096, at most
+ *                 what one workgroup's LDS holds).
+ *   dense_limit   base primes below this are marked by a whole wavefront per
+ *                 prime (64 lanes on 64 consecutive multiples); primes at or
+ *                 above it by one lane per prime.  Clamped to >= 37.
+ *   bucket_limit  base primes at or above this are not scanned per segment:
+ *                 their hits are first sorted into per-segment buckets in HBM
+ *                 (batched and plain paths).  0 = never use buckets.
+ *   bucket_depth  entries per segment bucket (0 = automatic).
+ *   block_threads threads per workgroup: 256, 512 or 1024.
+ *   wg_per_cu     resident workgroups per compute unit for persistent
+ *                 launches (0 = as many as LDS allows). */
+typedef struct sieve_tuning {
+    uint32_t seg_bits;
+    uint32_t dense_limit;
+    uint32_t bucket_limit;
+    uint32_t bucket_depth;
+    uint32_t block_threads;
+    uint32_t wg_per_cu;
+} sieve_tuning;
+
+/* What a call on [lo, hi) will do, from sieve_plan (pure host arithmetic). */
+typedef struct sieve_plan_info {
+    uint64_t nbits;        /* odd integers in [lo, hi) = bitmap bits */
+    uint64_t n_words;      /* uint32 words of the bitmap */
+    uint64_t sqrt_bound;   /* isqrt(hi - 1): largest possible base prime */
+    uint64_t n_segments;   /* LDS segments the range is cut into */
+    uint32_t seg_bits;     /* odd integers per segment (tuning resolved) */
+    uint32_t dense_limit;  /* resolved */
+    uint32_t block_threads;/* resolved */
+    uint32_t pad;
+} sieve_plan_info;
+
+/* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * device memory the batch and serving paths may hold at once (0 = 32 GiB).
+ * Builds the base-prime table on the device (primes <= 2^20) before
+ * returning.  Errors: SIEVE_EINVAL (ctx NULL), SIEVE_ENODEV (no such device,
+ * or not gfx950), SIEVE_ENOMEM, SIEVE_EDEVICE.  On success *ctx must be
+ * released with sieve_destroy. */
+SIEVE_API int sieve_create(sieve_ctx **ctx, int hip_device, uint64_t hbm_budget_bytes);
+
+/* Release a context and everything it owns.  Waits for its stream.
+ * NULL is accepted and ignored. */
+SIEVE_API int sieve_destroy(sieve_ctx *ctx);
+
+/* Static English text for a status code (never NULL). */
+SIEVE_API const char *sieve_strerror(int status);
+
+/* The hipError_t of the last failed HIP call on this context (0 if none). */
+SIEVE_API int sieve_last_hip_error(const sieve_ctx *ctx);
+
+/* Device time in milliseconds of the last sieve kernel this context launched
+ * (sieve_range_count, sieve_range_bitmap or sieve_batch), from HIP events
+ * recorded on the call's stream immediately before and after the launch.
+ * Waits for that kernel.  Errors: SIEVE_EINVAL (NULL arguments, or no launch
+ * yet), SIEVE_EDEVICE. */
+SIEVE_API int sieve_last_kernel_ms(sieve_ctx *ctx, double *ms);
+
+/* Read or replace the context's tuning.  set validates every field first
+ * (SIEVE_EINVAL leaves the old tuning in place). */
+SIEVE_API int sieve_get_tuning(const sieve_ctx *ctx, sieve_tuning *out);
+SIEVE_API int sieve_set_tuning(sieve_ctx *ctx, const sieve_tuning *tuning);
+
+/* Plan a call on [lo, hi) with the given tuning (NULL = all automatic) for
+ * a device with n_cu compute units and lds_bytes of LDS per workgroup.  Pure
+ * host arithmetic, no device needed.  Errors as for sieve_range_count. */
+SIEVE_API int sieve_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tuning, uint32_t n_cu,
+               uint32_t lds_bytes, sieve_plan_info *out);
+
+/* Number of uint32 words of the bitmap of [lo, hi):
+ * ceil((hi/2 - lo/2) / 32).  Pure; 0 when lo >= hi. */
+SIEVE_API uint64_t sieve_bitmap_words(uint64_t lo, uint64_t hi);
+
+/* The base primes (step A1): all primes p <= limit in ascending order,
+ * including 2, copied into the HOST buffer out[0 .. cap).  The table is
+ * computed on the device (a one-workgroup bootstrap sieve below 2^16, then the
+ * range sieve and a compaction kernel) and kept resident in the context.
+ * limit <= isqrt(SIEVE_MAX_HI) + 1.  out == NULL or cap == 0 is a size query:
+ * only *n_out is written.  Errors: SIEVE_EINVAL (ctx or n_out NULL),
+ * SIEVE_ERANGE (limit too large), SIEVE_EBUFSZ (cap < count; *n_out = count),
+ * SIEVE_ENOMEM, SIEVE_EDEVICE. */
+SIEVE_API int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint32_t *out, uint64_t cap,
+                      uint64_t *n_out);
+
+/* pi over [lo, hi) (steps A1-A6, A8): the number of primes p with
+ * lo <= p < hi.  No bitmap is written.  Blocks until *pi_out is valid.
+ * Errors: SIEVE_EINVAL (ctx or pi_out NULL, lo > hi), SIEVE_ERANGE,
+ * SIEVE_ENOMEM, SIEVE_EDEVICE. */
+SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *pi_out,
+                      void *stream);
+
+/* The odd-only prime bitmap of [lo, hi) (steps A1-A8) written to the DEVICE
+ * buffer d_words[0 .. n_words); words past sieve_bitmap_words(lo, hi) are not
+ * touched.  d_words must be 4-byte aligned.  With pi_out == NULL the call is
+ * asynchronous (ordered on `stream`); otherwise it blocks and stores pi.
+ * Errors: SIEVE_EINVAL (ctx NULL, d_words NULL with a non-empty range,
+ * misaligned d_words, lo > hi), SIEVE_ERANGE, SIEVE_EBUFSZ (n_words too
+ * small), SIEVE_ENOMEM, SIEVE_EDEVICE. */
+SIEVE_API int sieve_range_bitmap(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t *d_words,
+                       uint64_t n_words, uint64_t *pi_out, void *stream);
+
+/* One interval of a batch.  flags bit 0: write its bitmap at
+ * d_words[word_offset ..); the range's words must lie inside total_words. */
+typedef struct sieve_interval {
+    uint64_t lo;
+    uint64_t hi;
+    uint64_t word_offset;
+    uint32_t flags;
+    uint32_t pad;
+} sieve_interval;
+
+#define SIEVE_WANT_BITMAP 1u
+
+/* Many independent intervals in one persistent launch (the block partition
+ * of Section 3.1, Eq. 3, generalised to many ranges of uneven position and
+ * length): every (interval, segment) pair is one work item of a device work
+ * queue that resident workgroups drain.  iv is a HOST array of n intervals;
+ * pi_out is a HOST array of n counts (pi of each interval).  d_words may be
+ * NULL when no interval sets SIEVE_WANT_BITMAP.  Blocks until pi_out is
+ * valid.  Intervals may overlap in value; their bitmap word ranges must not
+ * overlap.  Errors: SIEVE_EINVAL (NULL pointers, lo > hi in any interval,
+ * overlapping or misaligned outputs), SIEVE_ERANGE, SIEVE_EBUFSZ (an
+ * interval's words exceed total_words), SIEVE_ENOMEM (work exceeds the HBM
+ * budget), SIEVE_EDEVICE. */
+SIEVE_API int sieve_batch(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
+                uint64_t total_words, uint64_t *pi_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIEVE_H */

@@ -1,0 +1,646 @@
+// Host runtime and C ABI of the exact range sieve (declared in sieve.h).
+//
+// The host side only validates arguments, plans segments and launches
+// kernels: base primes, marking, counting and compaction all run on the
+// device.  A context keeps the base-prime table resident in HBM (with a host
+// mirror used for planning) so that repeated calls pay for it once.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sieve.h"
+#include "sieve_internal.h"
+
+namespace {
+
+constexpr uint64_t kMaxPrimeLimit = 31622777;      // > isqrt(SIEVE_MAX_HI)
+constexpr uint64_t kDefaultPrimeLimit = 1u << 20;  // covers hi <= 1.0995e12
+constexpr uint32_t kSegGranuleWords = 128;         // 4096 bits
+constexpr uint32_t kDefaultMaxSegWords = 16384;    // 2^19 bits = 64 KiB of LDS
+constexpr uint64_t kDefaultBudget = 32ull << 30;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sieve_ctx {
+    int device = 0;
+    uint32_t n_cu = 0;
+    uint32_t lds_max = 0;  // LDS bytes one workgroup may use
+    uint32_t lds_per_cu = 0;
+    uint64_t hbm_budget = kDefaultBudget;
+    hipStream_t stream = nullptr;
+    sieve_tuning tuning{};
+    int last_hip = 0;
+
+    // base primes: all odd primes <= primes_limit, ascending
+    uint64_t primes_limit = 0;
+    std::vector<uint32_t> h_primes;
+    uint32_t *d_primes = nullptr;
+
+    unsigned long long *d_count = nullptr;
+    unsigned long long *h_count = nullptr;  // pinned
+
+    // events bracketing the last sieve kernel launch (range or batch)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    bool ev_valid = false;
+
+    // batch buffers, grown on demand
+    DevBuf b_iv, b_item, b_counts, b_queue;
+    std::vector<sv::BatchInterval> h_iv;
+    std::vector<uint32_t> h_item;
+    unsigned long long *h_counts = nullptr;  // pinned
+    size_t h_counts_cap = 0;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                    \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) {               \
+            (ctx)->last_hip = static_cast<int>(e_); \
+            return SIEVE_EDEVICE;             \
+        }                                     \
+    } while (0)
+
+uint64_t isqrt_u64(uint64_t n)
+{
+    if (n < 2)
+        return n;
+    uint64_t r = static_cast<uint64_t>(std::sqrt(static_cast<double>(n)));
+    while (r * r > n)
+        --r;
+    while ((r + 1) * (r + 1) <= n)
+        ++r;
+    return r;
+}
+
+uint32_t max_seg_words(uint32_t lds_bytes)
+{
+    if (lds_bytes <= sv::kTableWords * 4u)
+        return 0;
+    uint32_t w = lds_bytes / 4u - sv::kTableWords;
+    return w / kSegGranuleWords * kSegGranuleWords;
+}
+
+int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
+{
+    if (t.seg_bits) {
+        if (t.seg_bits % (kSegGranuleWords * 32) != 0)
+            return SIEVE_EINVAL;
+        if (t.seg_bits / 32 > max_seg_words(lds_bytes))
+            return SIEVE_EINVAL;
+    }
+    if (t.dense_limit > (1u << 20))
+        return SIEVE_EINVAL;
+    if (t.block_threads && t.block_threads != 256 && t.block_threads != 512 &&
+        t.block_threads != 1024)
+        return SIEVE_EINVAL;
+    if (t.bucket_limit != 0 || t.bucket_depth != 0)  // bucket path not built
+        return SIEVE_EINVAL;
+    if (t.wg_per_cu > 16)
+        return SIEVE_EINVAL;
+    return SIEVE_OK;
+}
+
+int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
+              sieve_plan_info *out)
+{
+    if (!out || lo > hi)
+        return SIEVE_EINVAL;
+    if (hi > SIEVE_MAX_HI)
+        return SIEVE_ERANGE;
+    sieve_tuning t{};
+    if (tu)
+        t = *tu;
+    if (int st = validate_tuning(t, lds_bytes))
+        return st;
+    if (n_cu == 0)
+        n_cu = 1;
+    sieve_plan_info p{};
+    p.nbits = hi / 2 - lo / 2;
+    p.n_words = (p.nbits + 31) / 32;
+    p.sqrt_bound = hi >= 2 ? isqrt_u64(hi - 1) : 0;
+    const uint32_t cap = std::min(max_seg_words(lds_bytes), kDefaultMaxSegWords);
+    if (cap == 0)
+        return SIEVE_EINVAL;
+    uint32_t sw;
+    if (t.seg_bits) {
+        sw = t.seg_bits / 32;
+    } else {
+        // enough segments for two workgroups per CU, within the LDS cap
+        uint64_t want = (p.n_words + 2ull * n_cu - 1) / (2ull * n_cu);
+        want = (want + kSegGranuleWords - 1) / kSegGranuleWords * kSegGranuleWords;
+        sw = static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(want, kSegGranuleWords), cap));
+    }
+    p.seg_bits = sw * 32;
+    p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 64;
+    p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
+    p.block_threads = t.block_threads ? t.block_threads : (sw >= 4096 ? 1024u : 256u);
+    p.n_segments = (p.n_words + sw - 1) / sw;
+    *out = p;
+    return SIEVE_OK;
+}
+
+// Build the device table of all odd primes <= limit (limit >= 2^16 - 1).
+int build_primes(sieve_ctx *c, uint64_t limit)
+{
+    hipStream_t s = c->stream;
+    uint32_t *d_boot = nullptr, *d_small = nullptr;
+    HIP_TRY(c, hipMalloc(&d_boot, sv::kBootstrapOddPrimes * sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc(&d_small, 4 * sizeof(uint32_t)));
+    int st = SIEVE_OK;
+    uint32_t *d_words = nullptr, *d_tmp = nullptr, *d_out = nullptr;
+    uint32_t total = 0;
+    do {
+        hipError_t e = sv::launch_bootstrap_primes(d_boot, d_small, s);
+        uint32_t boot_n = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&boot_n, d_small, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        if (boot_n != sv::kBootstrapOddPrimes) {
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        // The range sieve of [0, limit + 1) with the bootstrap primes as base
+        // primes, then a compaction of its bitmap.
+        const uint64_t hi = limit + 1;
+        sieve_plan_info pl{};
+        st = make_plan(0, hi, nullptr, c->n_cu, c->lds_max, &pl);
+        if (st)
+            break;
+        const uint64_t r = pl.sqrt_bound;  // < 2^16 since limit < 2^32
+        std::vector<uint32_t> boot(sv::kBootstrapOddPrimes);
+        e = hipMemcpy(boot.data(), d_boot, boot.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        const uint32_t n_odd = static_cast<uint32_t>(std::upper_bound(boot.begin(), boot.end(), r) - boot.begin());
+        const uint32_t n_mark = n_odd > sv::kPresievePrimes ? n_odd - sv::kPresievePrimes : 0;
+        const uint32_t n_dense_all = static_cast<uint32_t>(
+            std::lower_bound(boot.begin(), boot.end(), pl.dense_limit) - boot.begin());
+        const uint32_t n_dense = std::min(n_mark, n_dense_all > sv::kPresievePrimes ? n_dense_all - sv::kPresievePrimes : 0u);
+        const uint64_t out_cap = static_cast<uint64_t>(1.3 * hi / std::log(static_cast<double>(hi))) + 1024;
+        if ((e = hipMalloc(&d_words, pl.n_words * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&d_tmp, sv::compact_tmp_words(pl.n_words) * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&d_out, out_cap * sizeof(uint32_t))) != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_ENOMEM;
+            break;
+        }
+        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr};
+        sv::PrimeArgs pa{d_boot + sv::kPresievePrimes, n_dense, n_mark};
+        e = sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads, pl.n_segments, s);
+        if (e == hipSuccess)
+            e = sv::launch_compact(d_words, pl.n_words, 1, d_tmp, d_out, d_small, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&total, d_small, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        if (total > out_cap) {
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        std::vector<uint32_t> h(total);
+        e = hipMemcpy(h.data(), d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        // the bitmap of [0, limit] has no bit for 2: the list is the odd primes
+        if (c->d_primes)
+            (void)hipFree(c->d_primes);
+        c->d_primes = d_out;
+        d_out = nullptr;
+        c->h_primes.swap(h);
+        c->primes_limit = limit;
+    } while (false);
+    (void)hipFree(d_boot);
+    (void)hipFree(d_small);
+    if (d_words)
+        (void)hipFree(d_words);
+    if (d_tmp)
+        (void)hipFree(d_tmp);
+    if (d_out)
+        (void)hipFree(d_out);
+    return st;
+}
+
+int ensure_primes(sieve_ctx *c, uint64_t bound)
+{
+    if (bound <= c->primes_limit)
+        return SIEVE_OK;
+    if (bound > kMaxPrimeLimit)
+        return SIEVE_ERANGE;
+    uint64_t lim = std::max<uint64_t>(bound, 2 * c->primes_limit);
+    lim = std::max<uint64_t>(lim, sv::kBootstrapLimit);
+    lim = std::min<uint64_t>(lim, kMaxPrimeLimit);
+    return build_primes(c, lim);
+}
+
+// Marking primes for sieving with base-prime bound r: (count, dense count).
+void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32_t *n_mark,
+                    uint32_t *n_dense)
+{
+    const auto &v = c->h_primes;
+    const uint32_t n_odd = static_cast<uint32_t>(std::upper_bound(v.begin(), v.end(), r) - v.begin());
+    *n_mark = n_odd > sv::kPresievePrimes ? n_odd - sv::kPresievePrimes : 0;
+    const uint32_t nd = static_cast<uint32_t>(std::lower_bound(v.begin(), v.end(), dense_limit) - v.begin());
+    *n_dense = std::min(*n_mark, nd > sv::kPresievePrimes ? nd - sv::kPresievePrimes : 0u);
+}
+
+int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t *pi_out,
+              hipStream_t s)
+{
+    sieve_plan_info pl{};
+    if (int st = make_plan(lo, hi, &c->tuning, c->n_cu, c->lds_max, &pl))
+        return st;
+    const uint64_t two = (lo <= 2 && 2 < hi) ? 1 : 0;
+    if (pl.nbits == 0) {
+        if (pi_out)
+            *pi_out = two;
+        return SIEVE_OK;
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = ensure_primes(c, pl.sqrt_bound))
+        return st;
+    uint32_t n_mark = 0, n_dense = 0;
+    marking_primes(c, pl.sqrt_bound, pl.dense_limit, &n_mark, &n_dense);
+    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, pi_out ? c->d_count : nullptr};
+    sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, n_dense, n_mark};
+    if (pi_out)
+        HIP_TRY(c, hipMemsetAsync(c->d_count, 0, sizeof(unsigned long long), s));
+    c->ev_valid = false;
+    HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads, pl.n_segments, s));
+    HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+    c->ev_valid = true;
+    if (pi_out) {
+        HIP_TRY(c, hipMemcpyAsync(c->h_count, c->d_count, sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        *pi_out = *c->h_count + two;
+    }
+    return SIEVE_OK;
+}
+
+int grow(sieve_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes)
+        return SIEVE_OK;
+    const size_t want = std::max(bytes, b.bytes * 2);
+    if (b.p)
+        HIP_TRY(c, hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        c->last_hip = e;
+        b.p = nullptr;
+        return SIEVE_ENOMEM;
+    }
+    b.bytes = want;
+    return SIEVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sieve_strerror(int status)
+{
+    switch (status) {
+    case SIEVE_OK: return "success";
+    case SIEVE_EINVAL: return "invalid argument";
+    case SIEVE_ERANGE: return "range outside [0, 10^15]";
+    case SIEVE_ENOMEM: return "out of memory or over the HBM budget";
+    case SIEVE_EBUFSZ: return "output buffer too small";
+    case SIEVE_EDEVICE: return "HIP device error";
+    case SIEVE_ENODEV: return "no gfx950 device";
+    case SIEVE_EOVERFLOW: return "bucket pool overflow";
+    default: return "unknown status";
+    }
+}
+
+uint64_t sieve_bitmap_words(uint64_t lo, uint64_t hi)
+{
+    if (lo >= hi)
+        return 0;
+    return (hi / 2 - lo / 2 + 31) / 32;
+}
+
+int sieve_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tuning, uint32_t n_cu, uint32_t lds_bytes,
+               sieve_plan_info *out)
+{
+    return make_plan(lo, hi, tuning, n_cu, lds_bytes, out);
+}
+
+int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
+{
+    if (!out)
+        return SIEVE_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || hip_device < 0 || hip_device >= n)
+        return SIEVE_ENODEV;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess)
+        return SIEVE_ENODEV;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return SIEVE_ENODEV;
+    sieve_ctx *c = new (std::nothrow) sieve_ctx();
+    if (!c)
+        return SIEVE_ENOMEM;
+    c->device = hip_device;
+    c->n_cu = static_cast<uint32_t>(prop.multiProcessorCount);
+    c->lds_max = static_cast<uint32_t>(prop.sharedMemPerBlock);
+    c->lds_per_cu = static_cast<uint32_t>(prop.maxSharedMemoryPerMultiProcessor);
+    if (c->lds_per_cu < c->lds_max)
+        c->lds_per_cu = c->lds_max;
+    if (hbm_budget_bytes)
+        c->hbm_budget = hbm_budget_bytes;
+    int st = SIEVE_OK;
+    hipError_t e = hipSetDevice(hip_device);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMalloc(&c->d_count, sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipHostMalloc(&c->h_count, sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipEventCreate(&c->ev_start);
+    if (e == hipSuccess)
+        e = hipEventCreate(&c->ev_stop);
+    if (e != hipSuccess) {
+        c->last_hip = e;
+        st = SIEVE_EDEVICE;
+    }
+    if (st == SIEVE_OK)
+        st = ensure_primes(c, kDefaultPrimeLimit);
+    if (st != SIEVE_OK) {
+        sieve_destroy(c);
+        return st;
+    }
+    *out = c;
+    return SIEVE_OK;
+}
+
+int sieve_destroy(sieve_ctx *c)
+{
+    if (!c)
+        return SIEVE_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->b_iv, &c->b_item, &c->b_counts, &c->b_queue})
+        if (b->p)
+            (void)hipFree(b->p);
+    if (c->d_primes)
+        (void)hipFree(c->d_primes);
+    if (c->d_count)
+        (void)hipFree(c->d_count);
+    if (c->h_count)
+        (void)hipHostFree(c->h_count);
+    if (c->h_counts)
+        (void)hipHostFree(c->h_counts);
+    if (c->ev_start)
+        (void)hipEventDestroy(c->ev_start);
+    if (c->ev_stop)
+        (void)hipEventDestroy(c->ev_stop);
+    if (c->stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+    return SIEVE_OK;
+}
+
+int sieve_last_hip_error(const sieve_ctx *c)
+{
+    return c ? c->last_hip : 0;
+}
+
+int sieve_last_kernel_ms(sieve_ctx *c, double *ms)
+{
+    if (!c || !ms || !c->ev_valid)
+        return SIEVE_EINVAL;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipEventSynchronize(c->ev_stop));
+    float f = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&f, c->ev_start, c->ev_stop));
+    *ms = f;
+    return SIEVE_OK;
+}
+
+int sieve_get_tuning(const sieve_ctx *c, sieve_tuning *out)
+{
+    if (!c || !out)
+        return SIEVE_EINVAL;
+    *out = c->tuning;
+    return SIEVE_OK;
+}
+
+int sieve_set_tuning(sieve_ctx *c, const sieve_tuning *t)
+{
+    if (!c || !t)
+        return SIEVE_EINVAL;
+    if (int st = validate_tuning(*t, c->lds_max))
+        return st;
+    c->tuning = *t;
+    return SIEVE_OK;
+}
+
+int sieve_base_primes(sieve_ctx *c, uint64_t limit, uint32_t *out, uint64_t cap, uint64_t *n_out)
+{
+    if (!c || !n_out)
+        return SIEVE_EINVAL;
+    if (limit > kMaxPrimeLimit)
+        return SIEVE_ERANGE;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = ensure_primes(c, limit))
+        return st;
+    const auto &v = c->h_primes;
+    const uint64_t n_odd = static_cast<uint64_t>(std::upper_bound(v.begin(), v.end(), limit) - v.begin());
+    const uint64_t n = limit >= 2 ? n_odd + 1 : 0;
+    if (!out || cap == 0) {
+        *n_out = n;
+        return SIEVE_OK;
+    }
+    if (cap < n) {
+        *n_out = n;
+        return SIEVE_EBUFSZ;
+    }
+    if (n) {
+        out[0] = 2;
+        std::memcpy(out + 1, v.data(), n_odd * sizeof(uint32_t));
+    }
+    *n_out = n;
+    return SIEVE_OK;
+}
+
+int sieve_range_count(sieve_ctx *c, uint64_t lo, uint64_t hi, uint64_t *pi_out, void *stream)
+{
+    if (!c || !pi_out || lo > hi)
+        return SIEVE_EINVAL;
+    if (hi > SIEVE_MAX_HI)
+        return SIEVE_ERANGE;
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    return run_range(c, lo, hi, nullptr, pi_out, s);
+}
+
+int sieve_range_bitmap(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t n_words,
+                       uint64_t *pi_out, void *stream)
+{
+    if (!c || lo > hi)
+        return SIEVE_EINVAL;
+    if (hi > SIEVE_MAX_HI)
+        return SIEVE_ERANGE;
+    const uint64_t need = sieve_bitmap_words(lo, hi);
+    if (need && !d_words)
+        return SIEVE_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_words) % 4 != 0)
+        return SIEVE_EINVAL;
+    if (n_words < need)
+        return SIEVE_EBUFSZ;
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    return run_range(c, lo, hi, d_words, pi_out, s);
+}
+
+int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
+                uint64_t total_words, uint64_t *pi_out, void *stream)
+{
+    if (!c || (n && (!iv || !pi_out)))
+        return SIEVE_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_words) % 4 != 0)
+        return SIEVE_EINVAL;
+    if (n == 0)
+        return SIEVE_OK;
+    // validate every interval before any device work
+    sieve_plan_info ref{};
+    if (int st = make_plan(0, 0, &c->tuning, c->n_cu, c->lds_max, &ref))
+        return st;
+    const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
+    const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
+    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 64,
+                                          sv::kFirstMarkedPrime);
+    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : 1024;
+    std::vector<std::pair<uint64_t, uint64_t>> spans;
+    uint64_t max_bound = 0, items = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (iv[i].lo > iv[i].hi)
+            return SIEVE_EINVAL;
+        if (iv[i].hi > SIEVE_MAX_HI)
+            return SIEVE_ERANGE;
+        const uint64_t nw = sieve_bitmap_words(iv[i].lo, iv[i].hi);
+        if (iv[i].flags & SIEVE_WANT_BITMAP) {
+            if (nw && !d_words)
+                return SIEVE_EINVAL;
+            if (iv[i].word_offset > total_words || nw > total_words - iv[i].word_offset)
+                return SIEVE_EBUFSZ;
+            if (nw)
+                spans.emplace_back(iv[i].word_offset, iv[i].word_offset + nw);
+        }
+        if (iv[i].hi >= 2)
+            max_bound = std::max(max_bound, isqrt_u64(iv[i].hi - 1));
+        items += (nw + sw - 1) / sw;
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second)
+            return SIEVE_EINVAL;
+    if (items > 0xffffffffull)
+        return SIEVE_ERANGE;
+    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + items * sizeof(uint32_t) +
+                               n * sizeof(unsigned long long) + 256;
+    if (dev_bytes > c->hbm_budget)
+        return SIEVE_ENOMEM;
+
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = ensure_primes(c, max_bound))
+        return st;
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    c->h_iv.resize(n);
+    c->h_item.resize(items);
+    uint32_t next = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        sv::BatchInterval &b = c->h_iv[i];
+        const uint64_t lo = iv[i].lo, hi = iv[i].hi;
+        b.first_odd = (lo & ~1ull) + 1;
+        b.nbits = hi / 2 - lo / 2;
+        b.n_words = (b.nbits + 31) / 32;
+        b.word_offset = (iv[i].flags & SIEVE_WANT_BITMAP) ? iv[i].word_offset : ~0ull;
+        uint32_t nm = 0, nd = 0;
+        marking_primes(c, hi >= 2 ? isqrt_u64(hi - 1) : 0, dense_limit, &nm, &nd);
+        b.n_primes = nm;
+        b.n_dense = nd;
+        b.seg_begin = next;
+        b.pad = 0;
+        const uint32_t segs = static_cast<uint32_t>((b.n_words + sw - 1) / sw);
+        for (uint32_t k = 0; k < segs; ++k)
+            c->h_item[next + k] = i;
+        next += segs;
+    }
+    if (int st = grow(c, c->b_iv, n * sizeof(sv::BatchInterval)))
+        return st;
+    if (int st = grow(c, c->b_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
+        return st;
+    if (int st = grow(c, c->b_counts, n * sizeof(unsigned long long)))
+        return st;
+    if (int st = grow(c, c->b_queue, 256))
+        return st;
+    if (c->h_counts_cap < n) {
+        if (c->h_counts)
+            HIP_TRY(c, hipHostFree(c->h_counts));
+        c->h_counts = nullptr;
+        c->h_counts_cap = 0;
+        HIP_TRY(c, hipHostMalloc(&c->h_counts, n * sizeof(unsigned long long), hipHostMallocDefault));
+        c->h_counts_cap = n;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->b_iv.p, c->h_iv.data(), n * sizeof(sv::BatchInterval),
+                              hipMemcpyHostToDevice, s));
+    if (items)
+        HIP_TRY(c, hipMemcpyAsync(c->b_item.p, c->h_item.data(), items * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(c->b_counts.p, 0, n * sizeof(unsigned long long), s));
+    HIP_TRY(c, hipMemsetAsync(c->b_queue.p, 0, sizeof(uint32_t), s));
+    const uint32_t lds = sv::lds_bytes_for(sw);
+    uint32_t per_cu = std::max(1u, c->lds_per_cu / lds);
+    per_cu = std::min(per_cu, 2048u / threads);
+    if (c->tuning.wg_per_cu)
+        per_cu = std::min(per_cu, c->tuning.wg_per_cu);
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(items, uint64_t(per_cu) * c->n_cu));
+    c->ev_valid = false;
+    HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    HIP_TRY(c, sv::launch_batch(static_cast<const sv::BatchInterval *>(c->b_iv.p), n,
+                                static_cast<const uint32_t *>(c->b_item.p), static_cast<uint32_t>(items),
+                                c->d_primes + sv::kPresievePrimes, d_words,
+                                static_cast<unsigned long long *>(c->b_counts.p),
+                                static_cast<uint32_t *>(c->b_queue.p), sw, threads, blocks, s));
+    HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+    c->ev_valid = true;
+    HIP_TRY(c, hipMemcpyAsync(c->h_counts, c->b_counts.p, n * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < n; ++i)
+        pi_out[i] = c->h_counts[i] + ((iv[i].lo <= 2 && 2 < iv[i].hi) ? 1 : 0);
+    return SIEVE_OK;
+}
+
+}  // extern "C"

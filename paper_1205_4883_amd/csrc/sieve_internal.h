@@ -1,0 +1,70 @@
+// Internal interface between the host runtime (sieve_api.hip) and the
+// kernels (sieve_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sv {
+
+// Odd primes 3..31 are removed by the pre-sieve tables (three groups whose
+// products are 15015, 7429 and 899); the marking kernels start at the
+// eleventh odd prime, 37.
+constexpr uint32_t kPresievePrimes = 10;
+constexpr uint32_t kFirstMarkedPrime = 37;
+// LDS words taken by the three pre-sieve tables (each is its pattern's
+// period plus one spare word, rounded so the segment starts 16-byte aligned).
+constexpr uint32_t kTableWords = 736;
+// The bootstrap kernel sieves the odd integers below 2^16 in one workgroup.
+constexpr uint32_t kBootstrapLimit = 65536;
+constexpr uint32_t kBootstrapOddPrimes = 6541;  // odd primes below 2^16
+
+// One range as the segment kernels see it.
+struct RangeArgs {
+    uint64_t first_odd;  // the odd integer of bit 0: (lo & ~1) + 1
+    uint64_t nbits;      // odd integers in the range
+    uint64_t n_words;    // ceil(nbits / 32)
+    uint32_t *out;       // bitmap words of the range (word 0 = bit 0), or null
+    unsigned long long *count;  // += number of 1 bits (primes), or null
+};
+
+// The marking primes of one launch: odd primes >= 37, ascending.
+struct PrimeArgs {
+    const uint32_t *primes;
+    uint32_t n_dense;   // primes[0, n_dense) are marked a wavefront per prime
+    uint32_t n_primes;  // primes[0, n_primes) are used
+};
+
+// One interval of a batch, as uploaded to the device.
+struct BatchInterval {
+    uint64_t first_odd;
+    uint64_t nbits;
+    uint64_t n_words;
+    uint64_t word_offset;   // into the batch bitmap, or ~0 for count only
+    uint32_t n_primes;      // marking primes this interval needs
+    uint32_t n_dense;
+    uint32_t seg_begin;     // first work item of this interval
+    uint32_t pad;
+};
+
+// Launchers (sieve_kernels.hip).  All return the first HIP error.
+hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
+
+hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
+                        uint32_t block_threads, uint64_t n_segments, hipStream_t s);
+
+// Compaction of a bitmap (1 = prime) into the ascending list of the integers
+// its set bits stand for.  d_tmp needs compact_tmp_words(n_words) words.
+uint64_t compact_tmp_words(uint64_t n_words);
+hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t first_odd,
+                          uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
+
+hipError_t launch_batch(const BatchInterval *d_iv, uint32_t n_iv, const uint32_t *d_item_iv,
+                        uint32_t n_items, const uint32_t *d_primes, uint32_t *d_words,
+                        unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
+                        uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
+
+// Resident workgroups per CU the segment kernel reaches with this LDS use.
+uint32_t lds_bytes_for(uint32_t seg_words);
+
+}  // namespace sv

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libsieve.so (include/sieve.h).
+
+The functions carry the C names and only marshal arguments: every step of
+the sieve runs in the library's HIP kernels.  PyTorch is used for device
+memory (output tensors) and streams.  There is no fallback: if the library
+is missing or no gfx950 device is present, the calls fail loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsieve.so")
+
+SIEVE_OK = 0
+SIEVE_EINVAL = -1
+SIEVE_ERANGE = -2
+SIEVE_ENOMEM = -3
+SIEVE_EBUFSZ = -4
+SIEVE_EDEVICE = -5
+SIEVE_ENODEV = -6
+SIEVE_EOVERFLOW = -7
+SIEVE_MAX_HI = 10**15
+SIEVE_WANT_BITMAP = 1
+
+EXPORTED = [
+    "sieve_create", "sieve_destroy", "sieve_strerror", "sieve_last_hip_error",
+    "sieve_last_kernel_ms",
+    "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
+    "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
+]
+
+
+class sieve_tuning(ctypes.Structure):
+    _fields_ = [("seg_bits", ctypes.c_uint32), ("dense_limit", ctypes.c_uint32),
+                ("bucket_limit", ctypes.c_uint32), ("bucket_depth", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+
+
+class sieve_plan_info(ctypes.Structure):
+    _fields_ = [("nbits", ctypes.c_uint64), ("n_words", ctypes.c_uint64),
+                ("sqrt_bound", ctypes.c_uint64), ("n_segments", ctypes.c_uint64),
+                ("seg_bits", ctypes.c_uint32), ("dense_limit", ctypes.c_uint32),
+                ("block_threads", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class sieve_interval(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64),
+                ("word_offset", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+INTERVAL_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8"), ("word_offset", "<u8"),
+                           ("flags", "<u4"), ("pad", "<u4")])
+assert INTERVAL_DTYPE.itemsize == ctypes.sizeof(sieve_interval)
+
+
+class SieveError(RuntimeError):
+    def __init__(self, status, what=""):
+        msg = _lib().sieve_strerror(status).decode() if _LIB else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    u32, u64, vp, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.sieve_create.argtypes = [ctypes.POINTER(vp), i32, u64]
+    lib.sieve_destroy.argtypes = [vp]
+    lib.sieve_strerror.argtypes = [i32]
+    lib.sieve_strerror.restype = ctypes.c_char_p
+    lib.sieve_last_hip_error.argtypes = [vp]
+    lib.sieve_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.sieve_get_tuning.argtypes = [vp, ctypes.POINTER(sieve_tuning)]
+    lib.sieve_set_tuning.argtypes = [vp, ctypes.POINTER(sieve_tuning)]
+    lib.sieve_plan.argtypes = [u64, u64, ctypes.POINTER(sieve_tuning), u32, u32,
+                               ctypes.POINTER(sieve_plan_info)]
+    lib.sieve_bitmap_words.argtypes = [u64, u64]
+    lib.sieve_bitmap_words.restype = u64
+    lib.sieve_base_primes.argtypes = [vp, u64, vp, u64, u64p]
+    lib.sieve_range_count.argtypes = [vp, u64, u64, u64p, vp]
+    lib.sieve_range_bitmap.argtypes = [vp, u64, u64, vp, u64, u64p, vp]
+    lib.sieve_batch.argtypes = [vp, vp, u32, vp, u64, vp, vp]
+    for name in EXPORTED:
+        if name not in ("sieve_strerror", "sieve_bitmap_words"):
+            getattr(lib, name).restype = i32
+    _LIB = lib
+    return lib
+
+
+def _check(status, what):
+    if status != SIEVE_OK:
+        raise SieveError(status, what)
+
+
+# -- the C functions, same names -------------------------------------------
+
+def sieve_create(hip_device=0, hbm_budget_bytes=0):
+    ctx = ctypes.c_void_p()
+    _check(_lib().sieve_create(ctypes.byref(ctx), hip_device, hbm_budget_bytes), "sieve_create")
+    return ctx
+
+
+def sieve_destroy(ctx):
+    _check(_lib().sieve_destroy(ctx), "sieve_destroy")
+
+
+def sieve_strerror(status):
+    return _lib().sieve_strerror(status).decode()
+
+
+def sieve_last_hip_error(ctx):
+    return _lib().sieve_last_hip_error(ctx)
+
+
+def sieve_last_kernel_ms(ctx):
+    ms = ctypes.c_double(0.0)
+    _check(_lib().sieve_last_kernel_ms(ctx, ctypes.byref(ms)), "sieve_last_kernel_ms")
+    return ms.value
+
+
+def sieve_get_tuning(ctx):
+    t = sieve_tuning()
+    _check(_lib().sieve_get_tuning(ctx, ctypes.byref(t)), "sieve_get_tuning")
+    return {k: getattr(t, k) for k, _ in sieve_tuning._fields_}
+
+
+def sieve_set_tuning(ctx, **fields):
+    t = sieve_tuning(**fields)
+    _check(_lib().sieve_set_tuning(ctx, ctypes.byref(t)), "sieve_set_tuning")
+
+
+def sieve_plan(lo, hi, tuning=None, n_cu=256, lds_bytes=163840):
+    info = sieve_plan_info()
+    t = ctypes.byref(sieve_tuning(**tuning)) if tuning else None
+    _check(_lib().sieve_plan(lo, hi, t, n_cu, lds_bytes, ctypes.byref(info)), "sieve_plan")
+    return {k: getattr(info, k) for k, _ in sieve_plan_info._fields_ if k != "pad"}
+
+
+def sieve_bitmap_words(lo, hi):
+    return int(_lib().sieve_bitmap_words(lo, hi))
+
+
+def sieve_base_primes(ctx, limit):
+    """All primes <= limit (computed on the device) as a numpy uint32 array."""
+    n = ctypes.c_uint64(0)
+    _check(_lib().sieve_base_primes(ctx, limit, None, 0, ctypes.byref(n)), "sieve_base_primes")
+    out = np.zeros(max(1, n.value), dtype=np.uint32)
+    _check(_lib().sieve_base_primes(ctx, limit, out.ctypes.data, out.size, ctypes.byref(n)),
+           "sieve_base_primes")
+    return out[: n.value]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+
+
+def sieve_range_count(ctx, lo, hi, stream=None):
+    pi = ctypes.c_uint64(0)
+    _check(_lib().sieve_range_count(ctx, lo, hi, ctypes.byref(pi), _stream_ptr(stream)),
+           "sieve_range_count")
+    return pi.value
+
+
+def sieve_range_bitmap(ctx, lo, hi, d_words, n_words, want_pi=True, stream=None):
+    """d_words: device address (int) or a CUDA tensor; returns pi or None."""
+    ptr = d_words.data_ptr() if hasattr(d_words, "data_ptr") else d_words
+    pi = ctypes.c_uint64(0)
+    _check(_lib().sieve_range_bitmap(ctx, lo, hi, ctypes.c_void_p(ptr), n_words,
+                                     ctypes.byref(pi) if want_pi else None, _stream_ptr(stream)),
+           "sieve_range_bitmap")
+    return pi.value if want_pi else None
+
+
+def sieve_batch(ctx, intervals, d_words=None, total_words=0, stream=None):
+    """intervals: numpy array of INTERVAL_DTYPE.  Returns numpy uint64 pi per interval."""
+    iv = np.ascontiguousarray(intervals, dtype=INTERVAL_DTYPE)
+    pi = np.zeros(max(1, len(iv)), dtype=np.uint64)
+    ptr = d_words.data_ptr() if hasattr(d_words, "data_ptr") else (d_words or 0)
+    _check(_lib().sieve_batch(ctx, iv.ctypes.data, len(iv), ctypes.c_void_p(ptr), total_words,
+                              pi.ctypes.data, _stream_ptr(stream)), "sieve_batch")
+    return pi[: len(iv)]
+
+
+# -- convenience wrapper over torch tensors -----------------------------------
+
+class Sieve:
+    """A context on one GPU; outputs are torch tensors on that device."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.ctx = sieve_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ctx is not None:
+            sieve_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device)
+
+    def tuning(self, **fields):
+        if fields:
+            sieve_set_tuning(self.ctx, **fields)
+        return sieve_get_tuning(self.ctx)
+
+    def base_primes(self, limit):
+        return sieve_base_primes(self.ctx, limit)
+
+    def count(self, lo, hi):
+        return sieve_range_count(self.ctx, lo, hi, stream=self._stream())
+
+    def alloc_words(self, lo, hi):
+        n = sieve_bitmap_words(lo, hi)
+        return self.torch.empty(max(1, n), dtype=self.torch.int32, device=f"cuda:{self.device}")
+
+    def bitmap(self, lo, hi, out=None, want_pi=True):
+        """(words tensor, pi).  words is int32 with the layout of sieve.h."""
+        n = sieve_bitmap_words(lo, hi)
+        if out is None:
+            out = self.alloc_words(lo, hi)
+        pi = sieve_range_bitmap(self.ctx, lo, hi, out, out.numel(), want_pi, stream=self._stream())
+        return out[:n], pi
+
+    def batch(self, los, his, want_bitmap=False, out=None):
+        """Per-interval pi (numpy uint64) and, with want_bitmap, (words, offsets)."""
+        los = np.asarray(los, dtype=np.uint64)
+        his = np.asarray(his, dtype=np.uint64)
+        iv = np.zeros(len(los), dtype=INTERVAL_DTYPE)
+        iv["lo"], iv["hi"] = los, his
+        words = None
+        total = 0
+        if want_bitmap:
+            nw = his // 2 - los // 2
+            nw = (nw + 31) // 32
+            offs = np.zeros(len(los), dtype=np.uint64)
+            if len(los):
+                offs[1:] = np.cumsum(nw)[:-1]
+            total = int(nw.sum())
+            iv["word_offset"] = offs
+            iv["flags"] = SIEVE_WANT_BITMAP
+            words = out if out is not None else self.torch.empty(
+                max(1, total), dtype=self.torch.int32, device=f"cuda:{self.device}")
+        pi = sieve_batch(self.ctx, iv, words, words.numel() if words is not None else 0,
+                         stream=self._stream())
+        if want_bitmap:
+            return pi, words, iv["word_offset"].copy()
+        return pi

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every comparison is exact (bitmaps word for word, counts as integers): the
+sieve's result is a set of integers with one correct value per range
+(paper, Sections 1 and 3.1), so there is no tolerance.
+"""
+import random
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv_mod():
+    import paper_1205_4883_amd as sv
+
+    return sv
+
+
+@pytest.fixture(scope="module")
+def gpu(sv_mod):
+    import torch
+
+    assert torch.cuda.is_available()
+    s = sv_mod.Sieve(0)
+    yield s
+    s.close()
+
+
+def _cmp_bitmap(gpu, oracle_mod, lo, hi, threads=None):
+    print(f"case bitmap [{lo}, {hi})", flush=True)
+    words, pi = gpu.bitmap(lo, hi)
+    got = words.cpu().numpy().view(np.uint32)
+    ref, ref_pi = oracle_mod.bitmap(lo, hi, threads=threads)
+    assert pi == ref_pi, (lo, hi, pi, ref_pi)
+    if not np.array_equal(got, ref):
+        bad = np.nonzero(got != ref)[0]
+        raise AssertionError(f"[{lo},{hi}): {bad.size} words differ, first {bad[:5]} "
+                             f"got {got[bad[:5]]} want {ref[bad[:5]]}")
+    assert gpu.count(lo, hi) == ref_pi
+    return pi
+
+
+# -- the three single-range workloads at full size ----------------------------
+
+def test_c1_bitmap_2_to_1e7(gpu, oracle_mod):
+    assert _cmp_bitmap(gpu, oracle_mod, 2, 10**7) == 664579
+
+
+def test_c2_bitmap_2_to_1e9(gpu, oracle_mod):
+    assert _cmp_bitmap(gpu, oracle_mod, 2, 10**9) == 50847534
+
+
+def test_c3_count_2_to_1e10(gpu, oracle_mod):
+    print("case count [2, 1e10)", flush=True)
+    pi = gpu.count(2, 10**10)
+    assert pi == 455052511
+    assert pi == oracle_mod.count(2, 10**10)
+
+
+def test_c3_sampled_bits_at_full_size(gpu, oracle_mod):
+    # the count-only launch of [2, 1e10) writes no bitmap; sample the
+    # bitmap launch of the same range at scattered windows
+    print("case sampled bitmap [2, 1e10)", flush=True)
+    lo, hi = 2, 10**10
+    n = gpu.torch.cuda
+    words, pi = gpu.bitmap(lo, hi)
+    assert pi == 455052511
+    rng = random.Random(11)
+    for _ in range(24):
+        w0 = rng.randrange(0, words.numel() - 2048)
+        a = 2 + 64 * w0  # [a, a + 64*2048) has bit 0 at a + 1 = 3 + 64*w0
+        got = words[w0:w0 + 2048].cpu().numpy().view(np.uint32)
+        ref, _ = oracle_mod.bitmap(a, a + 64 * 2048)
+        assert np.array_equal(got, ref[:2048]), w0
+    del words
+    n.empty_cache()
+
+
+# -- small and edge ranges ----------------------------------------------------
+
+def test_every_tiny_range(gpu, oracle_mod):
+    print("case all ranges in [0, 130]", flush=True)
+    for lo in range(0, 131):
+        for hi in range(lo, 131):
+            words, pi = gpu.bitmap(lo, hi)
+            ref, ref_pi = oracle_mod.bitmap(lo, hi)
+            assert pi == ref_pi, (lo, hi)
+            assert np.array_equal(words.cpu().numpy().view(np.uint32), ref), (lo, hi)
+
+
+@pytest.mark.parametrize("lo,hi", [
+    (0, 1), (0, 2), (0, 3), (1, 3), (2, 3), (3, 4), (0, 8), (2, 8), (5, 6), (4, 5),
+    (0, 121), (0, 122), (120, 122), (0, 961), (0, 962), (0, 1369), (0, 1370),
+    (999999999989, 999999999990), (999999999990, 1000000000039),
+    (999999999990, 1000000000040), (10**12 - 10**6, 10**12 + 10**6),
+    (10**15 - 3 * 10**6, 10**15), (10**15 - 1, 10**15),
+])
+def test_edge_ranges(gpu, oracle_mod, lo, hi):
+    _cmp_bitmap(gpu, oracle_mod, lo, hi)
+
+
+def test_known_endpoint_counts(gpu):
+    assert gpu.count(999999999990, 1000000000039) == 0
+    assert gpu.count(999999999990, 1000000000040) == 1
+    assert gpu.count(999999999989, 999999999990) == 1
+    assert gpu.count(0, 2**32) == 203280221
+    for n in [561, 1105, 1729, 2465, 2821, 6601, 8911]:
+        assert gpu.count(n, n + 1) == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_ranges_across_magnitudes(gpu, oracle_mod, seed):
+    rng = random.Random(100 + seed)
+    for _ in range(6):
+        e = rng.uniform(2, 15)
+        lo = min(int(10**e), 10**15 - 1)
+        ln = int(10 ** rng.uniform(0, 6.7))
+        hi = min(lo + ln, 10**15)
+        _cmp_bitmap(gpu, oracle_mod, lo, hi)
+
+
+def test_segment_boundary_straddles(gpu, oracle_mod):
+    # plan the segment size, then cut ranges at +-1 around segment edges
+    import paper_1205_4883_amd as sv
+
+    gpu.tuning(seg_bits=4096, dense_limit=0, block_threads=256)
+    try:
+        base = 10**11
+        seg_ints = 2 * 4096
+        for k in [1, 2, 7]:
+            for d in [-3, -2, -1, 0, 1, 2, 3]:
+                lo = base
+                hi = base + k * seg_ints + d
+                _cmp_bitmap(gpu, oracle_mod, lo, hi)
+                _cmp_bitmap(gpu, oracle_mod, lo + 1, hi)
+    finally:
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0)
+    assert sv.sieve_get_tuning(gpu.ctx)["seg_bits"] == 0
+
+
+@pytest.mark.parametrize("seg_bits,dense_limit,threads", [
+    (4096, 37, 256), (4096, 64, 512), (32768, 0, 1024), (131072, 37, 256),
+    (524288, 0, 1024), (524288, 37, 1024), (524288, 2**20, 1024), (262144, 1000, 512),
+])
+def test_tuning_sweep(gpu, oracle_mod, seg_bits, dense_limit, threads):
+    gpu.tuning(seg_bits=seg_bits, dense_limit=dense_limit, block_threads=threads)
+    try:
+        for lo, hi in [(0, 3 * 10**6 + 17), (10**10 - 777, 10**10 + 5 * 10**6),
+                       (10**13 + 1, 10**13 + 2 * 10**6 + 3)]:
+            _cmp_bitmap(gpu, oracle_mod, lo, hi)
+        assert gpu.count(2, 10**9) == 50847534
+    finally:
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0)
+
+
+def test_additivity_on_gpu(gpu):
+    rng = random.Random(7)
+    for _ in range(30):
+        a = rng.randrange(0, 10**12)
+        c = a + rng.randrange(0, 5 * 10**7)
+        b = rng.randrange(a, c + 1)
+        assert gpu.count(a, c) == gpu.count(a, b) + gpu.count(b, c)
+
+
+# -- base primes -------------------------------------------------------------
+
+@pytest.mark.parametrize("limit", [0, 1, 2, 3, 100, 65535, 65536, 100000, 2**20, 3 * 10**6, 31622777])
+def test_base_primes(gpu, oracle_mod, limit):
+    got = gpu.base_primes(limit)
+    ref = oracle_mod.base_primes(limit)
+    assert np.array_equal(got, ref)
+
+
+# -- ABI behaviour on the device ---------------------------------------------
+
+def test_errors_leave_outputs_untouched(gpu, sv_mod):
+    import torch
+
+    buf = torch.full((8,), -1, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(sv_mod.SieveError) as e:
+        sv_mod.sieve_range_bitmap(gpu.ctx, 0, 1000, buf, 8)  # needs 16 words
+    assert e.value.status == sv_mod.sieve.SIEVE_EBUFSZ
+    with pytest.raises(sv_mod.SieveError) as e:
+        sv_mod.sieve_range_bitmap(gpu.ctx, 100, 10, buf, 8)
+    assert e.value.status == sv_mod.sieve.SIEVE_EINVAL
+    with pytest.raises(sv_mod.SieveError) as e:
+        sv_mod.sieve_range_count(gpu.ctx, 0, 10**15 + 1)
+    assert e.value.status == sv_mod.sieve.SIEVE_ERANGE
+    with pytest.raises(sv_mod.SieveError) as e:
+        sv_mod.sieve_range_bitmap(gpu.ctx, 0, 100, buf.data_ptr() + 2, 4)
+    assert e.value.status == sv_mod.sieve.SIEVE_EINVAL
+    torch.cuda.synchronize()
+    assert (buf.cpu() == -1).all()
+    assert sv_mod.sieve_range_count(gpu.ctx, 10, 10) == 0
+    assert sv_mod.sieve_range_count(gpu.ctx, 2, 2) == 0
+
+
+def test_bitmap_leaves_words_past_the_range(gpu, oracle_mod, sv_mod):
+    import torch
+
+    buf = torch.full((200,), 0x5A5A5A5A, dtype=torch.int32, device="cuda:0")
+    pi = sv_mod.sieve_range_bitmap(gpu.ctx, 1000, 1000 + 64 * 100 - 30, buf, 200)
+    ref, ref_pi = oracle_mod.bitmap(1000, 1000 + 64 * 100 - 30)
+    host = buf.cpu().numpy().view(np.uint32)
+    assert pi == ref_pi
+    assert np.array_equal(host[:100], ref)
+    assert (host[100:] == 0x5A5A5A5A).all()
+
+
+def test_async_bitmap_on_torch_stream(gpu, oracle_mod, sv_mod):
+    import torch
+
+    lo, hi = 10**11, 10**11 + 10**7
+    out = gpu.alloc_words(lo, hi)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        sv_mod.sieve_range_bitmap(gpu.ctx, lo, hi, out, out.numel(), want_pi=False, stream=st)
+        host = out.cpu()  # ordered after the sieve on the same stream
+    st.synchronize()
+    ref, _ = oracle_mod.bitmap(lo, hi)
+    assert np.array_equal(host.numpy().view(np.uint32), ref)
+
+
+# -- batch -----------------------------------------------------------------
+
+def test_batch_matches_oracle(gpu, oracle_mod):
+    rng = np.random.default_rng(3)
+    n = 300
+    los = np.floor(np.exp(rng.uniform(np.log(1), np.log(1e12), n))).astype(np.uint64)
+    lens = np.floor(np.exp(rng.uniform(np.log(1), np.log(3e6), n))).astype(np.uint64)
+    his = los + lens
+    los[:5] = [0, 1, 2, 3, 5]
+    his[:5] = [0, 2, 3, 1000, 1_000_003]
+    print(f"case batch of {n}", flush=True)
+    pi, words, offs = gpu.batch(los, his, want_bitmap=True)
+    host = words.cpu().numpy().view(np.uint32)
+    for i in range(n):
+        lo, hi = int(los[i]), int(his[i])
+        ref, ref_pi = oracle_mod.bitmap(lo, hi)
+        assert int(pi[i]) == ref_pi, (i, lo, hi)
+        o = int(offs[i])
+        assert np.array_equal(host[o:o + ref.size], ref), (i, lo, hi)
+    pi2 = gpu.batch(los, his, want_bitmap=False)
+    assert np.array_equal(pi, pi2)
