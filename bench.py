@@ -100,6 +100,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--seg-bits", type=int, default=0, help="tuning: odd integers per segment")
+    ap.add_argument("--dense-limit", type=int, default=0, help="tuning: wave-per-prime bound")
+    ap.add_argument("--block-threads", type=int, default=0, help="tuning: threads per workgroup")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the "
+                         "reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -109,11 +115,23 @@ def main():
     import numpy as np
     import torch
 
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 3}), flush=True)
+        return
+
     import paper_1205_4883_amd as sv
 
     wl = WORKLOADS[args.workload]
     lo, hi = wl["lo"], wl["hi"]
     s = sv.Sieve(0)
+    if args.seg_bits or args.dense_limit or args.block_threads:
+        s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads)
     stream = torch.cuda.current_stream(0)
     out = s.alloc_words(lo, hi) if wl["bitmap"] else None
 
@@ -140,7 +158,7 @@ def main():
     marks, lane_ops, words = algorithmic_lds_ops(primes, lo, hi)
     k_ms = float(np.mean(kernel_ms))
     achieved = lane_ops / (k_ms * 1e-3)
-    plan = sv.sieve_plan(lo, hi)
+    plan = sv.sieve_plan(lo, hi, tuning=s.tuning())
     roof = {
         "bound": "lds",
         "achieved": achieved / 1e9,

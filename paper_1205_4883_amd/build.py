@@ -16,6 +16,9 @@ def hipcc_command(out):
     return [
         hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         "-fvisibility=hidden", "-Wall",
+        # the largest LDS segment cannot reach the 8-waves-per-SIMD register
+        # target; that is expected, not a problem
+        "-Wno-pass-failed",
         # never let the compiler form packed fp32 ops
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE, "-I", CSRC,

@@ -42,8 +42,16 @@ struct sieve_ctx {
     uint64_t primes_limit = 0;
     std::vector<uint32_t> h_primes;
     uint32_t *d_primes = nullptr;
+    double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
 
-    unsigned long long *d_count = nullptr;
+    // Per-call device words {count, segment queue}: kSlots slots used in
+    // turn, each guarded by an event so that an asynchronous call still
+    // running on another stream never sees its slot reset.
+    static constexpr int kSlots = 16;
+    unsigned long long *d_count = nullptr;  // 2 * kSlots words
+    hipEvent_t slot_done[kSlots] = {};
+    bool slot_used[kSlots] = {};
+    int next_slot = 0;
     unsigned long long *h_count = nullptr;  // pinned
 
     // events bracketing the last sieve kernel launch (range or batch)
@@ -81,12 +89,14 @@ uint64_t isqrt_u64(uint64_t n)
     return r;
 }
 
+// Largest segment (words) a workgroup with lds_bytes of LDS can hold.
 uint32_t max_seg_words(uint32_t lds_bytes)
 {
-    if (lds_bytes <= sv::kTableWords * 4u)
-        return 0;
-    uint32_t w = lds_bytes / 4u - sv::kTableWords;
-    return w / kSegGranuleWords * kSegGranuleWords;
+    uint32_t best = 0;
+    for (uint32_t w = kSegGranuleWords; w <= sv::max_seg_words(); w += kSegGranuleWords)
+        if (sv::lds_bytes_for(w) <= lds_bytes)
+            best = w;
+    return best;
 }
 
 int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
@@ -140,12 +150,33 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         sw = static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(want, kSegGranuleWords), cap));
     }
     p.seg_bits = sw * 32;
-    p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 64;
+    p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 512;
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
-    p.block_threads = t.block_threads ? t.block_threads : (sw >= 4096 ? 1024u : 256u);
+    p.block_threads = t.block_threads ? t.block_threads : (sw >= 2048 ? 512u : 256u);
     p.n_segments = (p.n_words + sw - 1) / sw;
     *out = p;
     return SIEVE_OK;
+}
+
+// The next per-call {count, queue} slot, once its previous user has finished.
+int take_slot(sieve_ctx *c, unsigned long long **words)
+{
+    const int i = c->next_slot;
+    c->next_slot = (i + 1) % sieve_ctx::kSlots;
+    if (c->slot_used[i])
+        HIP_TRY(c, hipEventSynchronize(c->slot_done[i]));
+    c->slot_used[i] = false;
+    *words = c->d_count + 2 * i;
+    return i;
+}
+
+// Workgroups that fit on the device at once for a plan.
+uint32_t resident_blocks(const sieve_ctx *c, const sieve_plan_info &pl, bool write)
+{
+    uint32_t per_cu = sv::range_blocks_per_cu(pl.seg_bits / 32, pl.block_threads, write);
+    if (c->tuning.wg_per_cu)
+        per_cu = std::min(per_cu, c->tuning.wg_per_cu);
+    return std::max(per_cu, 1u) * c->n_cu;
 }
 
 // Build the device table of all odd primes <= limit (limit >= 2^16 - 1).
@@ -153,13 +184,18 @@ int build_primes(sieve_ctx *c, uint64_t limit)
 {
     hipStream_t s = c->stream;
     uint32_t *d_boot = nullptr, *d_small = nullptr;
+    double *d_boot_inv = nullptr;
     HIP_TRY(c, hipMalloc(&d_boot, sv::kBootstrapOddPrimes * sizeof(uint32_t)));
     HIP_TRY(c, hipMalloc(&d_small, 4 * sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc(&d_boot_inv, sv::kBootstrapOddPrimes * sizeof(double)));
     int st = SIEVE_OK;
     uint32_t *d_words = nullptr, *d_tmp = nullptr, *d_out = nullptr;
+    double *d_out_inv = nullptr;
     uint32_t total = 0;
     do {
         hipError_t e = sv::launch_bootstrap_primes(d_boot, d_small, s);
+        if (e == hipSuccess)
+            e = sv::launch_reciprocals(d_boot, sv::kBootstrapOddPrimes, d_boot_inv, s);
         uint32_t boot_n = 0;
         if (e == hipSuccess)
             e = hipMemcpyAsync(&boot_n, d_small, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -202,9 +238,26 @@ int build_primes(sieve_ctx *c, uint64_t limit)
             st = SIEVE_ENOMEM;
             break;
         }
-        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr};
-        sv::PrimeArgs pa{d_boot + sv::kPresievePrimes, n_dense, n_mark};
-        e = sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads, pl.n_segments, s);
+        unsigned long long *slot = nullptr;
+        const int si = take_slot(c, &slot);
+        if (si < 0) {
+            st = si;
+            break;
+        }
+        uint32_t *queue = reinterpret_cast<uint32_t *>(slot + 1);
+        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr, queue};
+        e = hipMemsetAsync(queue, 0, sizeof(uint32_t), s);
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
+        sv::PrimeArgs pa{d_boot + sv::kPresievePrimes, d_boot_inv + sv::kPresievePrimes, n_dense, n_mark};
+        e = sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
+                             static_cast<uint32_t>(pl.n_segments), resident_blocks(c, pl, true), s);
+        if (e == hipSuccess)
+            e = hipEventRecord(c->slot_done[si], s);
+        c->slot_used[si] = true;
         if (e == hipSuccess)
             e = sv::launch_compact(d_words, pl.n_words, 1, d_tmp, d_out, d_small, s);
         if (e == hipSuccess)
@@ -222,6 +275,12 @@ int build_primes(sieve_ctx *c, uint64_t limit)
         }
         std::vector<uint32_t> h(total);
         e = hipMemcpy(h.data(), d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMalloc(&d_out_inv, std::max<uint32_t>(total, 1) * sizeof(double));
+        if (e == hipSuccess)
+            e = sv::launch_reciprocals(d_out, total, d_out_inv, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             c->last_hip = e;
             st = SIEVE_EDEVICE;
@@ -230,13 +289,20 @@ int build_primes(sieve_ctx *c, uint64_t limit)
         // the bitmap of [0, limit] has no bit for 2: the list is the odd primes
         if (c->d_primes)
             (void)hipFree(c->d_primes);
+        if (c->d_inv)
+            (void)hipFree(c->d_inv);
         c->d_primes = d_out;
+        c->d_inv = d_out_inv;
         d_out = nullptr;
+        d_out_inv = nullptr;
         c->h_primes.swap(h);
         c->primes_limit = limit;
     } while (false);
     (void)hipFree(d_boot);
     (void)hipFree(d_small);
+    (void)hipFree(d_boot_inv);
+    if (d_out_inv)
+        (void)hipFree(d_out_inv);
     if (d_words)
         (void)hipFree(d_words);
     if (d_tmp)
@@ -281,23 +347,33 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
             *pi_out = two;
         return SIEVE_OK;
     }
+    if (pl.n_segments > 0xffffffffull)
+        return SIEVE_ERANGE;
     HIP_TRY(c, hipSetDevice(c->device));
     if (int st = ensure_primes(c, pl.sqrt_bound))
         return st;
     uint32_t n_mark = 0, n_dense = 0;
     marking_primes(c, pl.sqrt_bound, pl.dense_limit, &n_mark, &n_dense);
-    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, pi_out ? c->d_count : nullptr};
-    sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, n_dense, n_mark};
-    if (pi_out)
-        HIP_TRY(c, hipMemsetAsync(c->d_count, 0, sizeof(unsigned long long), s));
+    unsigned long long *slot = nullptr;
+    const int si = take_slot(c, &slot);
+    if (si < 0)
+        return si;
+    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, pi_out ? slot : nullptr,
+                     reinterpret_cast<uint32_t *>(slot + 1)};
+    sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
+    HIP_TRY(c, hipMemsetAsync(slot, 0, 2 * sizeof(unsigned long long), s));
     c->ev_valid = false;
     HIP_TRY(c, hipEventRecord(c->ev_start, s));
-    HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads, pl.n_segments, s));
+    HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
+                                static_cast<uint32_t>(pl.n_segments),
+                                resident_blocks(c, pl, d_words != nullptr), s));
     HIP_TRY(c, hipEventRecord(c->ev_stop, s));
     c->ev_valid = true;
+    if (pi_out)
+        HIP_TRY(c, hipMemcpyAsync(c->h_count, slot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
+    c->slot_used[si] = true;
     if (pi_out) {
-        HIP_TRY(c, hipMemcpyAsync(c->h_count, c->d_count, sizeof(unsigned long long),
-                                  hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         *pi_out = *c->h_count + two;
     }
@@ -383,7 +459,9 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipMalloc(&c->d_count, sizeof(unsigned long long));
+        e = hipMalloc(&c->d_count, 2 * sieve_ctx::kSlots * sizeof(unsigned long long));
+    for (int i = 0; i < sieve_ctx::kSlots && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc(&c->h_count, sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess)
@@ -416,8 +494,13 @@ int sieve_destroy(sieve_ctx *c)
             (void)hipFree(b->p);
     if (c->d_primes)
         (void)hipFree(c->d_primes);
+    if (c->d_inv)
+        (void)hipFree(c->d_inv);
     if (c->d_count)
         (void)hipFree(c->d_count);
+    for (int i = 0; i < sieve_ctx::kSlots; ++i)
+        if (c->slot_done[i])
+            (void)hipEventDestroy(c->slot_done[i]);
     if (c->h_count)
         (void)hipHostFree(c->h_count);
     if (c->h_counts)
@@ -538,9 +621,9 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
         return st;
     const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
     const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
-    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 64,
+    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
                                           sv::kFirstMarkedPrime);
-    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : 1024;
+    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : 512;
     std::vector<std::pair<uint64_t, uint64_t>> spans;
     uint64_t max_bound = 0, items = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -620,9 +703,7 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
                                   hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(c->b_counts.p, 0, n * sizeof(unsigned long long), s));
     HIP_TRY(c, hipMemsetAsync(c->b_queue.p, 0, sizeof(uint32_t), s));
-    const uint32_t lds = sv::lds_bytes_for(sw);
-    uint32_t per_cu = std::max(1u, c->lds_per_cu / lds);
-    per_cu = std::min(per_cu, 2048u / threads);
+    uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(sw, threads));
     if (c->tuning.wg_per_cu)
         per_cu = std::min(per_cu, c->tuning.wg_per_cu);
     const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(items, uint64_t(per_cu) * c->n_cu));
@@ -630,7 +711,7 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     HIP_TRY(c, hipEventRecord(c->ev_start, s));
     HIP_TRY(c, sv::launch_batch(static_cast<const sv::BatchInterval *>(c->b_iv.p), n,
                                 static_cast<const uint32_t *>(c->b_item.p), static_cast<uint32_t>(items),
-                                c->d_primes + sv::kPresievePrimes, d_words,
+                                c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, d_words,
                                 static_cast<unsigned long long *>(c->b_counts.p),
                                 static_cast<uint32_t *>(c->b_queue.p), sw, threads, blocks, s));
     HIP_TRY(c, hipEventRecord(c->ev_stop, s));

@@ -26,11 +26,13 @@ struct RangeArgs {
     uint64_t n_words;    // ceil(nbits / 32)
     uint32_t *out;       // bitmap words of the range (word 0 = bit 0), or null
     unsigned long long *count;  // += number of 1 bits (primes), or null
+    uint32_t *queue;     // segment counter, zero at launch
 };
 
 // The marking primes of one launch: odd primes >= 37, ascending.
 struct PrimeArgs {
     const uint32_t *primes;
+    const double *inv;  // inv[i] = 1 / primes[i], rounded to double
     uint32_t n_dense;   // primes[0, n_dense) are marked a wavefront per prime
     uint32_t n_primes;  // primes[0, n_primes) are used
 };
@@ -50,8 +52,13 @@ struct BatchInterval {
 // Launchers (sieve_kernels.hip).  All return the first HIP error.
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
 
+// Grid: min(n_segments, max_blocks) workgroups draining the segment queue.
 hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
-                        uint32_t block_threads, uint64_t n_segments, hipStream_t s);
+                        uint32_t block_threads, uint32_t n_segments, uint32_t max_blocks,
+                        hipStream_t s);
+
+// inv[i] = 1.0 / primes[i] for i < n.
+hipError_t launch_reciprocals(const uint32_t *d_primes, uint32_t n, double *d_inv, hipStream_t s);
 
 // Compaction of a bitmap (1 = prime) into the ascending list of the integers
 // its set bits stand for.  d_tmp needs compact_tmp_words(n_words) words.
@@ -60,11 +67,21 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
 
 hipError_t launch_batch(const BatchInterval *d_iv, uint32_t n_iv, const uint32_t *d_item_iv,
-                        uint32_t n_items, const uint32_t *d_primes, uint32_t *d_words,
+                        uint32_t n_items, const uint32_t *d_primes, const double *d_inv,
+                        uint32_t *d_words,
                         unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
 
-// Resident workgroups per CU the segment kernel reaches with this LDS use.
+// The segment kernels are built for a few static LDS sizes: the smallest
+// capacity (in words) that holds seg_words (0 if none), the LDS bytes a
+// workgroup then uses, and the largest segment supported.
+uint32_t seg_capacity_for(uint32_t seg_words);
 uint32_t lds_bytes_for(uint32_t seg_words);
+uint32_t max_seg_words();
+
+// Workgroups of the range / batch kernel that fit on one CU at once (the HIP
+// occupancy calculator: LDS, VGPR and SGPR limits).
+uint32_t range_blocks_per_cu(uint32_t seg_words, uint32_t threads, bool write);
+uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads);
 
 }  // namespace sv

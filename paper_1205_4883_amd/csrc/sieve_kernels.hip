@@ -8,18 +8,26 @@
 //   1. pre-sieve: the multiples of 3..31 are ORed in from three periodic
 //      bit patterns held in LDS (products 3*5*7*11*13, 17*19*23, 29*31),
 //      one funnel shift per pattern per word, no atomics;
-//   2. dense primes (37 <= p < dense_limit): one wavefront per prime, lane k
-//      marks multiples k, k+64, k+128, ... of the prime's first odd multiple
-//      in the segment.  64*p bits is a whole number of words, so each lane's
-//      bit position inside a word never changes and its word address grows by
-//      2p per mark: one LDS atomic OR and one add per mark;
-//   3. sparse primes: one lane per prime walks its few multiples.
+//   2. dense primes (37 <= p < dense_limit): one wavefront per prime.  Only
+//      the multiples p*m with 3 not dividing m are crossed off (3 | m is
+//      already covered by the pre-sieve); over the odd m these form 64
+//      classes modulo 96 odd steps, one per lane.  96*p bits is a whole
+//      number of words (3p), so a lane's bit inside its word never changes
+//      and its word moves by 3p per mark: one LDS atomic OR and one add;
+//   3. sparse primes: one lane per prime walks the multiples p*m with m
+//      prime to 15 (a wheel of period 30, gaps 6,4,2,4,2,4,6,2), so 8 of
+//      every 15 odd multiples are visited.
 // Then every thread counts the unmarked bits of its words (popcount plus a
 // wavefront shuffle reduction) and, for bitmap output, stores them to HBM.
 //
 // Crossing off starts at max(p*p, first odd multiple in the segment), so a
 // base prime never marks itself; the pre-sieve does mark 3..31 themselves and
 // leaves 1 unmarked, which the first word of a range corrects.
+//
+// LDS bank behaviour on gfx950 (32 banks of 4 bytes; each 32-lane half of a
+// wave is served separately) sets the cost of the scattered atomic ORs; the
+// wheel cuts their number, and the fixed-bit lane layout keeps the VALU work
+// per dense mark at one add.
 #include "sieve_internal.h"
 
 namespace sv {
@@ -34,6 +42,25 @@ constexpr uint32_t kWA = (kLA - 1) / 32 + 2;  // 471
 constexpr uint32_t kWB = (kLB - 1) / 32 + 2;  // 234
 constexpr uint32_t kWC = (kLC - 1) / 32 + 2;  // 30
 static_assert(kWA + kWB + kWC <= kTableWords, "pre-sieve tables exceed their LDS area");
+
+// Odd residues r mod 30 prime to 15, as a bit mask.
+constexpr uint32_t kWheelMask = (1u << 1) | (1u << 7) | (1u << 11) | (1u << 13) | (1u << 17) |
+                                (1u << 19) | (1u << 23) | (1u << 29);
+// Gaps between consecutive such residues, in odd steps (2 each), starting
+// after residue 1: 3,2,1,2,1,2,3,1 as 2-bit fields, repeated twice so that a
+// 2-bit rotation of the 32-bit word walks the cycle.
+constexpr uint32_t kWheelGaps16 = 3u | (2u << 2) | (1u << 4) | (2u << 6) | (1u << 8) | (2u << 10) |
+                                  (3u << 12) | (1u << 14);
+constexpr uint32_t kWheelGaps = kWheelGaps16 | (kWheelGaps16 << 16);
+
+// a * b + c with a, b < 2^24: one full-rate VALU op (the compiler would
+// otherwise pick a 64-bit multiply-add for a 32-bit product).
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
 
 __device__ __forceinline__ void lds_or(uint32_t *word, uint32_t mask)
 {
@@ -75,35 +102,122 @@ __device__ __forceinline__ uint32_t pattern_at(const uint32_t *tab, uint32_t j)
     return __builtin_amdgcn_alignbit(tab[k + 1], tab[k], j);
 }
 
-// n mod p for n < 2^53 and odd p < 2^25, through a double quotient.  n and
-// p are exact in double; the rounded quotient is at most one above the true
-// floor, which the final correction removes.
-__device__ __forceinline__ uint32_t mod_u64(uint64_t n, uint32_t p)
+// The first odd multiple m0*p of p with m0*p >= n0 and m0 >= p (crossing off
+// starts at p*p), for the segment whose bit 0 is the odd integer n0.
+//   off: its bit offset in the segment (at least lim_bits when past the
+//        segment);
+//   m30: m0 mod 30.
+// nf = n0 as a double (exact: n0 < 2^53) and inv = 1/p rounded to double.
+// floor(nf * inv) is within one of floor(n0 / p) (the product's relative
+// error is below 2^-52 and n0 / p < 2^48), and the remainder n0 - q*p is an
+// integer below 2^27 in magnitude, which an fma yields exactly; one
+// correction step then makes q exact.
+struct Start {
+    uint32_t off;
+    uint32_t m30;
+};
+
+__device__ __forceinline__ Start first_multiple(uint64_t n0, double nf, uint32_t p, double inv,
+                                                uint32_t lim_bits)
 {
-    const double q = floor(static_cast<double>(n) / static_cast<double>(p));
-    int64_t r = static_cast<int64_t>(n - static_cast<uint64_t>(q) * p);
-    if (r < 0)
-        r += p;
-    else if (r >= static_cast<int64_t>(p))
-        r -= p;
-    return static_cast<uint32_t>(r);
+    const double pf = static_cast<double>(p);
+    double q = floor(nf * inv);
+    double r = fma(-q, pf, nf);
+    if (r < 0.0) {
+        r += pf;
+        q -= 1.0;
+    } else if (r >= pf) {
+        r -= pf;
+        q += 1.0;
+    }
+    // k = ceil(n0 / p): the first multiplier with k*p >= n0
+    uint32_t d = 0;  // k*p - n0
+    if (r > 0.0) {
+        d = p - static_cast<uint32_t>(r);
+        q += 1.0;
+    }
+    const double t = floor(q * (1.0 / 30.0));
+    int32_t k30 = static_cast<int32_t>(fma(-t, 30.0, q));  // exact, within one period of [0, 30)
+    if (k30 < 0)
+        k30 += 30;
+    else if (k30 >= 30)
+        k30 -= 30;
+    if ((k30 & 1) == 0) {  // n0 is odd, so an even k gives an even multiple: take the next
+        d += p;
+        k30 += 1;
+    }
+    Start s{d >> 1, static_cast<uint32_t>(k30)};
+    if (pf * pf > nf) {  // p*p lies past n0 (both exact in double): start there, m0 = p
+        const uint64_t o2 = (static_cast<uint64_t>(p) * p - n0) >> 1;
+        s.off = o2 < lim_bits ? static_cast<uint32_t>(o2) : lim_bits;
+        s.m30 = p % 30u;
+    }
+    return s;
 }
 
-// Bit offset, inside the segment whose bit 0 is the odd integer n0, of the
-// first odd multiple m of p with m >= n0 and m >= p*p.  Returns at least
-// lim_bits when no such multiple falls before bit lim_bits.
-__device__ __forceinline__ uint32_t first_offset(uint64_t n0, uint32_t p, uint32_t lim_bits)
+// Dense marking of one prime by a whole wavefront.  The odd multiples
+// m0 + 2i (in units of p) with i = m0 (mod 3) are multiples of 3p and are
+// skipped; lane l takes the l-th remaining class c_l of i modulo 96 and marks
+// i = c_l, c_l + 96, c_l + 192, ...  A lane's first word is (s + c_l*p) >> 5
+// and each mark moves it by 96*p bits = 3p words at a fixed bit.  Lane 63 has
+// the largest class and lanes start less than 3p words apart, so the loop is
+// driven by lane 63's word (a scalar) and each lane needs at most one guarded
+// extra mark.
+__device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t p, uint32_t s,
+                                           uint32_t m30, uint32_t lane)
 {
-    const uint32_t r = mod_u64(n0, p);
-    uint32_t d = r ? p - r : 0;  // n0 + d is the first multiple >= n0
-    if (d & 1)                   // n0 is odd, so n0 + d is even: take the next one
-        d += p;
-    const uint64_t p2 = static_cast<uint64_t>(p) * p;
-    if (n0 + d < p2) {
-        const uint64_t off = (p2 - n0) >> 1;
-        return off < lim_bits ? static_cast<uint32_t>(off) : lim_bits;
+    const uint32_t r3 = m30 % 3u;  // skip i = r3 (mod 3)
+    const uint32_t a = r3 == 1 ? 1u : 0u;
+    const uint32_t b = r3 == 0 ? 1u : 0u;
+    const uint32_t c = lane + ((lane + a) >> 1) + b;
+    const uint32_t o = s + c * p;
+    const uint32_t mask = 1u << (o & 31);
+    uint32_t *ptr = seg + (o >> 5);
+    const uint32_t step = 3 * p;
+    uint32_t w = (s + (94u + a + b) * p) >> 5;  // lane 63: c = 63 + ((63 + a) >> 1) + b
+    for (; w + 3 * step < sw; w += 4 * step) {
+        uint32_t *p1 = ptr + step;
+        uint32_t *p2 = p1 + step;
+        uint32_t *p3 = p2 + step;
+        lds_or(ptr, mask);
+        lds_or(p1, mask);
+        lds_or(p2, mask);
+        lds_or(p3, mask);
+        ptr = p3 + step;
     }
-    return d >> 1;
+    for (; w < sw; w += step) {
+        lds_or(ptr, mask);
+        ptr += step;
+    }
+    if (ptr < seg + sw)
+        lds_or(ptr, mask);
+}
+
+// Sparse marking of one prime by one lane: the multiples p*m with m prime to
+// 15, from the segment's first odd multiple (bit offset o, m mod 30 = m30).
+__device__ __forceinline__ void mark_sparse(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
+                                            uint32_t m30)
+{
+    // step to the first m prime to 15 (at most two odd steps)
+    while (((kWheelMask >> m30) & 1u) == 0) {
+        m30 += 2;
+        o += p;
+    }
+    const uint32_t idx = __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;  // position in the cycle
+    uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
+    if (p < (1u << 24)) {  // gap * p as a full-rate 24-bit multiply-add
+        while (o < lim_bits) {
+            lds_or(seg + (o >> 5), 1u << (o & 31));
+            o = mad_u24(g & 3u, p, o);
+            g = __builtin_amdgcn_alignbit(g, g, 2);
+        }
+    } else {
+        while (o < lim_bits) {
+            lds_or(seg + (o >> 5), 1u << (o & 31));
+            o += (g & 3u) * p;
+            g = __builtin_amdgcn_alignbit(g, g, 2);
+        }
+    }
 }
 
 // The first word of a range: 1 is not prime; 3..31 are primes that the
@@ -135,8 +249,8 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 template <bool kWrite>
 __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
                               uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
-                              const uint32_t *primes, uint32_t n_dense, uint32_t n_primes,
-                              uint32_t *out, unsigned long long *count)
+                              const uint32_t *primes, const double *inv, uint32_t n_dense,
+                              uint32_t n_primes, uint32_t *out, unsigned long long *count)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
@@ -145,6 +259,7 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
     const uint32_t sw = left < seg_words_max ? static_cast<uint32_t>(left) : seg_words_max;
     const uint32_t lim_bits = sw * 32;
     const uint64_t n0 = first_odd + 64 * w0;  // odd integer of the segment's bit 0
+    const double nf = static_cast<double>(n0);
 
     // 1. pre-sieve.  Bit g of the segment is the odd integer 2x + 1 with
     //    x = (n0 >> 1) + g; pattern phases are x mod L.
@@ -173,36 +288,32 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
 
     // 2a. dense primes: one wavefront per prime.  Lane l of wave w computes
     //     the start of prime r*64*nw + l*nw + w, so each wave gets an
-    //     interleaved, evenly weighted share of the primes.
+    //     interleaved, evenly weighted share of the primes; the wave then
+    //     marks its (up to) 64 primes one after another.
     {
         const uint32_t lane = t & 63;
         const uint32_t wave = t >> 6;
         const uint32_t nw = nthreads >> 6;
         for (uint32_t r0 = 0; r0 + wave < n_dense; r0 += 64 * nw) {
             const uint32_t i = r0 + lane * nw + wave;
-            uint32_t p = 0, s0 = 0;
+            uint32_t p = 0, s0 = 0, m30 = 0;
             if (i < n_dense) {
                 p = primes[i];
-                s0 = first_offset(n0, p, lim_bits);
+                const Start st = first_multiple(n0, nf, p, inv[i], lim_bits);
+                s0 = st.off;
+                m30 = st.m30;
             }
-            for (int l = 0; l < 64; ++l) {
-                const uint32_t pl = __builtin_amdgcn_readlane(p, l);
-                if (pl == 0)
-                    break;
-                const uint32_t sl = __builtin_amdgcn_readlane(s0, l);
-                const uint32_t o = sl + lane * pl;
-                const uint32_t mask = 1u << (o & 31);
-                const uint32_t step = 2 * pl;  // 64 * p bits = 2p words
-                for (uint32_t a = o >> 5; a < sw; a += step)
-                    lds_or(seg_lds + a, mask);
-            }
+            const uint32_t cnt = min(64u, (n_dense - r0 - wave + nw - 1) / nw);
+            for (uint32_t l = 0; l < cnt; ++l)
+                mark_dense(seg_lds, sw, __builtin_amdgcn_readlane(p, l),
+                           __builtin_amdgcn_readlane(s0, l), __builtin_amdgcn_readlane(m30, l), lane);
         }
     }
     // 2b. sparse primes: one lane per prime.
     for (uint32_t i = n_dense + t; i < n_primes; i += nthreads) {
         const uint32_t p = primes[i];
-        for (uint32_t o = first_offset(n0, p, lim_bits); o < lim_bits; o += p)
-            lds_or(seg_lds + (o >> 5), 1u << (o & 31));
+        const Start st = first_multiple(n0, nf, p, inv[i], lim_bits);
+        mark_sparse(seg_lds, lim_bits, p, st.off, st.m30);
     }
     __syncthreads();
 
@@ -226,29 +337,45 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
     __syncthreads();  // the LDS segment is reused by the next segment
 }
 
-template <bool kWrite>
-__global__ void __launch_bounds__(1024) range_kernel(RangeArgs r, PrimeArgs pa, uint32_t seg_words,
-                                                      uint64_t n_segments)
+// Resident workgroups pop segment numbers from a device counter (r.queue,
+// zero at launch) until every segment is taken, so the grid size need not
+// match the number of workgroups that fit on the device.  The LDS segment is a
+// static array of kSegMax words, so LDS addresses are compile-time offsets; a
+// launch may use any seg_words <= kSegMax.
+// (Registers are capped so that eight waves fit per SIMD where LDS allows.)
+template <uint32_t kSegMax, bool kWrite>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) range_kernel(RangeArgs r, PrimeArgs pa, uint32_t seg_words,
+                                                      uint32_t n_segments)
 {
-    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t lds[kTableWords + kSegMax];
+    __shared__ uint32_t seg_sh;
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
-    __syncthreads();
-    for (uint64_t s = blockIdx.x; s < n_segments; s += gridDim.x)
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            seg_sh = atomicAdd(r.queue, 1u);
+        __syncthreads();
+        const uint32_t s = seg_sh;
+        if (s >= n_segments)
+            break;
         sieve_segment<kWrite>(tabs, seg, seg_words, s, r.first_odd, r.nbits, r.n_words, pa.primes,
-                              pa.n_dense, pa.n_primes, r.out, r.count);
+                              pa.inv, pa.n_dense, pa.n_primes, r.out, r.count);
+    }
 }
 
 // Persistent batch kernel: workgroups pop (interval, segment) items from a
 // device counter until the queue is empty.  Every workgroup leaves the loop
 // once the counter passes n_items, so the grid always drains.
-__global__ void __launch_bounds__(1024) batch_kernel(const BatchInterval *ivs, const uint32_t *item_iv,
+template <uint32_t kSegMax>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(const BatchInterval *ivs, const uint32_t *item_iv,
                                                       uint32_t n_items, const uint32_t *primes,
-                                                      uint32_t *words, unsigned long long *counts,
-                                                      uint32_t *queue, uint32_t seg_words)
+                                                      const double *inv, uint32_t *words,
+                                                      unsigned long long *counts, uint32_t *queue,
+                                                      uint32_t seg_words)
 {
-    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
@@ -266,10 +393,10 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchInterval *ivs, c
         const uint64_t s = item - iv.seg_begin;
         if (iv.word_offset != ~0ull)
             sieve_segment<true>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes,
-                                iv.n_dense, iv.n_primes, words + iv.word_offset, counts + k);
+                                inv, iv.n_dense, iv.n_primes, words + iv.word_offset, counts + k);
         else
             sieve_segment<false>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes,
-                                 iv.n_dense, iv.n_primes, nullptr, counts + k);
+                                 inv, iv.n_dense, iv.n_primes, nullptr, counts + k);
     }
 }
 
@@ -418,11 +545,35 @@ __global__ void __launch_bounds__(kCompactThreads) compact_write_kernel(const ui
     }
 }
 
+__global__ void __launch_bounds__(256) reciprocal_kernel(const uint32_t *primes, uint32_t n, double *inv)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        inv[i] = 1.0 / static_cast<double>(primes[i]);
+}
+
+// Static LDS sizes the segment kernels are built for (words of segment).
+constexpr uint32_t kSegSizes[] = {512, 2048, 8192, 16384, 32768};
+
 }  // namespace
+
+uint32_t seg_capacity_for(uint32_t seg_words)
+{
+    for (uint32_t c : kSegSizes)
+        if (seg_words <= c)
+            return c;
+    return 0;
+}
 
 uint32_t lds_bytes_for(uint32_t seg_words)
 {
-    return (kTableWords + seg_words) * 4u;
+    const uint32_t cap = seg_capacity_for(seg_words);
+    return cap ? (kTableWords + cap) * 4u : 0u;
+}
+
+uint32_t max_seg_words()
+{
+    return kSegSizes[sizeof(kSegSizes) / sizeof(kSegSizes[0]) - 1];
 }
 
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s)
@@ -431,19 +582,87 @@ hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
-                        uint32_t block_threads, uint64_t n_segments, hipStream_t s)
+hipError_t launch_reciprocals(const uint32_t *d_primes, uint32_t n, double *d_inv, hipStream_t s)
 {
-    const uint32_t lds = lds_bytes_for(seg_words);
-    const uint64_t grid = n_segments;  // one workgroup per segment
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(reciprocal_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_primes, n, d_inv);
+    return hipGetLastError();
+}
+
+namespace {
+template <uint32_t kSegMax>
+void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words, uint32_t threads,
+                      uint32_t n_segments, uint32_t grid, hipStream_t s)
+{
+    if (r.out)
+        hipLaunchKernelGGL((range_kernel<kSegMax, true>), dim3(grid), dim3(threads), 0, s, r, p, seg_words,
+                           n_segments);
+    else
+        hipLaunchKernelGGL((range_kernel<kSegMax, false>), dim3(grid), dim3(threads), 0, s, r, p, seg_words,
+                           n_segments);
+}
+
+template <uint32_t kSegMax>
+void launch_batch_cap(const BatchInterval *d_iv, const uint32_t *d_item_iv, uint32_t n_items,
+                      const uint32_t *d_primes, const double *d_inv, uint32_t *d_words,
+                      unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
+                      uint32_t threads, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_iv, d_item_iv, n_items,
+                       d_primes, d_inv, d_words, d_counts, d_queue, seg_words);
+}
+}  // namespace
+
+namespace {
+template <typename K>
+uint32_t blocks_per_cu(K kernel, uint32_t threads)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, static_cast<int>(threads), 0) != hipSuccess)
+        return 1;
+    return n > 0 ? static_cast<uint32_t>(n) : 1u;
+}
+}  // namespace
+
+uint32_t range_blocks_per_cu(uint32_t seg_words, uint32_t threads, bool write)
+{
+    switch (seg_capacity_for(seg_words)) {
+    case 512: return write ? blocks_per_cu(range_kernel<512, true>, threads) : blocks_per_cu(range_kernel<512, false>, threads);
+    case 2048: return write ? blocks_per_cu(range_kernel<2048, true>, threads) : blocks_per_cu(range_kernel<2048, false>, threads);
+    case 8192: return write ? blocks_per_cu(range_kernel<8192, true>, threads) : blocks_per_cu(range_kernel<8192, false>, threads);
+    case 16384: return write ? blocks_per_cu(range_kernel<16384, true>, threads) : blocks_per_cu(range_kernel<16384, false>, threads);
+    case 32768: return write ? blocks_per_cu(range_kernel<32768, true>, threads) : blocks_per_cu(range_kernel<32768, false>, threads);
+    default: return 1;
+    }
+}
+
+uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
+{
+    switch (seg_capacity_for(seg_words)) {
+    case 512: return blocks_per_cu(batch_kernel<512>, threads);
+    case 2048: return blocks_per_cu(batch_kernel<2048>, threads);
+    case 8192: return blocks_per_cu(batch_kernel<8192>, threads);
+    case 16384: return blocks_per_cu(batch_kernel<16384>, threads);
+    case 32768: return blocks_per_cu(batch_kernel<32768>, threads);
+    default: return 1;
+    }
+}
+
+hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
+                        uint32_t block_threads, uint32_t n_segments, uint32_t max_blocks, hipStream_t s)
+{
+    const uint32_t grid = n_segments < max_blocks ? n_segments : max_blocks;
     if (grid == 0)
         return hipSuccess;
-    if (r.out)
-        hipLaunchKernelGGL(range_kernel<true>, dim3(static_cast<uint32_t>(grid)), dim3(block_threads),
-                           lds, s, r, p, seg_words, n_segments);
-    else
-        hipLaunchKernelGGL(range_kernel<false>, dim3(static_cast<uint32_t>(grid)), dim3(block_threads),
-                           lds, s, r, p, seg_words, n_segments);
+    switch (seg_capacity_for(seg_words)) {
+    case 512: launch_range_cap<512>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    case 2048: launch_range_cap<2048>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    case 8192: launch_range_cap<8192>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    case 16384: launch_range_cap<16384>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    case 32768: launch_range_cap<32768>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -467,15 +686,21 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
 }
 
 hipError_t launch_batch(const BatchInterval *d_iv, uint32_t n_iv, const uint32_t *d_item_iv,
-                        uint32_t n_items, const uint32_t *d_primes, uint32_t *d_words,
+                        uint32_t n_items, const uint32_t *d_primes, const double *d_inv, uint32_t *d_words,
                         unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_blocks, hipStream_t s)
 {
     (void)n_iv;
     if (n_items == 0 || n_blocks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(batch_kernel, dim3(n_blocks), dim3(block_threads), lds_bytes_for(seg_words), s,
-                       d_iv, d_item_iv, n_items, d_primes, d_words, d_counts, d_queue, seg_words);
+    switch (seg_capacity_for(seg_words)) {
+    case 512: launch_batch_cap<512>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    case 2048: launch_batch_cap<2048>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    case 8192: launch_batch_cap<8192>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    case 16384: launch_batch_cap<16384>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    case 32768: launch_batch_cap<32768>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -245,3 +245,23 @@ def test_batch_matches_oracle(gpu, oracle_mod):
         assert np.array_equal(host[o:o + ref.size], ref), (i, lo, hi)
     pi2 = gpu.batch(los, his, want_bitmap=False)
     assert np.array_equal(pi, pi2)
+
+
+def test_async_bitmaps_on_several_streams(gpu, oracle_mod, sv_mod):
+    # asynchronous calls on different streams overlap on the device; each must
+    # keep its own segment queue
+    import torch
+
+    ranges = [(10**9 + 17 * k * 10**6, 10**9 + 17 * k * 10**6 + 3 * 10**6 + k) for k in range(20)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    outs = []
+    for k, (lo, hi) in enumerate(ranges):
+        st = streams[k % 4]
+        out = gpu.alloc_words(lo, hi)
+        with torch.cuda.stream(st):
+            sv_mod.sieve_range_bitmap(gpu.ctx, lo, hi, out, out.numel(), want_pi=False, stream=st)
+        outs.append((out, st))
+    torch.cuda.synchronize()
+    for (lo, hi), (out, _) in zip(ranges, outs):
+        ref, _ = oracle_mod.bitmap(lo, hi)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32)[:ref.size], ref), (lo, hi)
