@@ -79,6 +79,60 @@ def load_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def run_batch(sv, torch, s, steps, warmup, check_plain=True):
+    """The batched workload: 4096 seeded intervals, per-interval pi and packed
+    bitmaps from one sieve_batch call (one graph launch), against the same
+    intervals sieved one sieve_range_bitmap call at a time on one stream."""
+    import numpy as np
+
+    from paper_1205_4883_amd import workloads
+
+    los, his = workloads.batch_intervals(0)
+    n = len(los)
+    nw = (his // 2 - los // 2 + 31) // 32
+    offs = np.zeros(n, dtype=np.uint64)
+    offs[1:] = np.cumsum(nw)[:-1]
+    total = int(nw.sum())
+    iv = np.zeros(n, dtype=sv.INTERVAL_DTYPE)
+    iv["lo"], iv["hi"], iv["word_offset"], iv["flags"] = los, his, offs, 1
+    words = torch.empty(total, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream(0)
+    for _ in range(warmup):
+        pi = sv.sieve_batch(s.ctx, iv, words, total, stream=stream)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pi = sv.sieve_batch(s.ctx, iv, words, total, stream=stream)
+        kms.append(sv.sieve_last_kernel_ms(s.ctx))
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    ints = int((his - los).sum())
+    rec = {"workload": "batched sieve: 4096 intervals [a, a+L), a log-uniform in [1e6, 1e12], "
+                       "L log-uniform in [1e4, 1e8], seed 0; per-interval pi and packed bitmaps",
+           "intervals": n, "integers": ints, "bitmap_bytes": 4 * total,
+           "inputs_sha256": workloads.fingerprint(los, his),
+           "ms_per_batch": 1e3 * t_batch, "graph_ms": float(np.mean(kms)),
+           "ints_per_s": ints / t_batch, "pi_sum": int(pi.sum())}
+    if check_plain:
+        # the same outputs, one plain call per interval (pi returned per call)
+        base = words.data_ptr()
+        pis = np.zeros(n, dtype=np.uint64)
+        sv.sieve_range_bitmap(s.ctx, int(los[0]), int(his[0]), base, int(nw[0]), True, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            pis[i] = sv.sieve_range_bitmap(s.ctx, int(los[i]), int(his[i]), base + 4 * int(offs[i]),
+                                           int(nw[i]), True, stream=stream)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        assert np.array_equal(pis, pi), "batched and plain counts differ"
+        rec.update({"ms_plain_sequential": 1e3 * t_plain, "speedup_vs_plain": t_plain / t_batch})
+    del words
+    torch.cuda.empty_cache()
+    return rec
+
+
 def cpu_baseline(lo, hi, expect_pi):
     import oracle  # CPU-baseline leg only
 
@@ -98,7 +152,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-plain comparison in the default line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--seg-bits", type=int, default=0, help="tuning: odd integers per segment")
     ap.add_argument("--dense-limit", type=int, default=0, help="tuning: wave-per-prime bound")
@@ -126,6 +182,20 @@ def main():
         return
 
     import paper_1205_4883_amd as sv
+
+    if args.workload == "c4":
+        s = sv.Sieve(0)
+        if args.seg_bits or args.dense_limit or args.block_threads:
+            s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
+                     block_threads=args.block_threads)
+        b = run_batch(sv, torch, s, args.steps, args.warmup)
+        s.close()
+        print(json.dumps({
+            "metric": METRIC, "value": b["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_batch"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic", "config": {"workload": b["workload"]}, "batch": b}), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     lo, hi = wl["lo"], wl["hi"]
@@ -192,6 +262,8 @@ def main():
                    "block_threads": plan["block_threads"], "n_segments": plan["n_segments"]},
         "roofline": roof,
     }
+    if args.workload == "c3" and not args.no_batch:
+        rec["batch"] = run_batch(sv, torch, s, steps=3, warmup=1)
     s.close()
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"])

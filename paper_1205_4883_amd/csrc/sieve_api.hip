@@ -26,6 +26,26 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+struct HostBuf {  // pinned host memory
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Everything a captured batch graph bakes in.
+struct GraphKey {
+    const void *iv, *item, *hdr, *counts, *h_counts, *primes, *inv;
+    uint32_t *words;
+    uint32_t seg_words, threads, blocks, max_intervals;
+    size_t counts_bytes;
+    bool operator==(const GraphKey &o) const
+    {
+        return iv == o.iv && item == o.item && hdr == o.hdr && counts == o.counts &&
+               h_counts == o.h_counts && primes == o.primes && inv == o.inv && words == o.words &&
+               seg_words == o.seg_words && threads == o.threads && blocks == o.blocks &&
+               max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
+    }
+};
+
 }  // namespace
 
 struct sieve_ctx {
@@ -58,12 +78,16 @@ struct sieve_ctx {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     bool ev_valid = false;
 
-    // batch buffers, grown on demand
-    DevBuf b_iv, b_item, b_counts, b_queue;
-    std::vector<sv::BatchInterval> h_iv;
-    std::vector<uint32_t> h_item;
-    unsigned long long *h_counts = nullptr;  // pinned
-    size_t h_counts_cap = 0;
+    // batch buffers, grown on demand; host staging is pinned so that the
+    // uploads are asynchronous
+    DevBuf b_iv, b_item, b_counts, b_hdr;
+    HostBuf s_iv, s_item, s_counts, s_hdr;
+    std::vector<uint32_t> order;
+
+    // the captured batch graph (reset kernel, batch kernel, count readback)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key{};
 };
 
 namespace {
@@ -399,6 +423,70 @@ int grow(sieve_ctx *c, DevBuf &b, size_t bytes)
     return SIEVE_OK;
 }
 
+int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes)
+        return SIEVE_OK;
+    const size_t want = std::max(bytes, b.bytes * 2);
+    if (b.p)
+        HIP_TRY(c, hipHostFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        c->last_hip = e;
+        b.p = nullptr;
+        return SIEVE_ENOMEM;
+    }
+    b.bytes = want;
+    return SIEVE_OK;
+}
+
+void drop_graph(sieve_ctx *c)
+{
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Capture the batch launch sequence on the context's own stream (capture runs
+// nothing) and instantiate it; the graph may then be launched on any stream.
+int capture_batch_graph(sieve_ctx *c, const GraphKey &k)
+{
+    drop_graph(c);
+    hipStream_t cs = c->stream;
+    HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = sv::launch_batch(static_cast<const sv::BatchInterval *>(k.iv),
+                                    static_cast<const uint32_t *>(k.item),
+                                    static_cast<sv::BatchHeader *>(const_cast<void *>(k.hdr)),
+                                    k.max_intervals, static_cast<const uint32_t *>(k.primes),
+                                    static_cast<const double *>(k.inv), k.words,
+                                    static_cast<unsigned long long *>(const_cast<void *>(k.counts)),
+                                    k.seg_words, k.threads, k.blocks, cs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<void *>(k.h_counts), k.counts, k.counts_bytes,
+                           hipMemcpyDeviceToHost, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess)
+        e = e2;
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        c->graph_exec = nullptr;
+        c->last_hip = e;
+        return SIEVE_EDEVICE;
+    }
+    c->graph = g;
+    c->graph_key = k;
+    return SIEVE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -489,9 +577,13 @@ int sieve_destroy(sieve_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->b_iv, &c->b_item, &c->b_counts, &c->b_queue})
+    drop_graph(c);
+    for (DevBuf *b : {&c->b_iv, &c->b_item, &c->b_counts, &c->b_hdr})
         if (b->p)
             (void)hipFree(b->p);
+    for (HostBuf *b : {&c->s_iv, &c->s_item, &c->s_counts, &c->s_hdr})
+        if (b->p)
+            (void)hipHostFree(b->p);
     if (c->d_primes)
         (void)hipFree(c->d_primes);
     if (c->d_inv)
@@ -503,8 +595,6 @@ int sieve_destroy(sieve_ctx *c)
             (void)hipEventDestroy(c->slot_done[i]);
     if (c->h_count)
         (void)hipHostFree(c->h_count);
-    if (c->h_counts)
-        (void)hipHostFree(c->h_counts);
     if (c->ev_start)
         (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop)
@@ -616,14 +706,13 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     if (n == 0)
         return SIEVE_OK;
     // validate every interval before any device work
-    sieve_plan_info ref{};
-    if (int st = make_plan(0, 0, &c->tuning, c->n_cu, c->lds_max, &ref))
+    if (int st = validate_tuning(c->tuning, c->lds_max))
         return st;
     const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
     const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
     const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
                                           sv::kFirstMarkedPrime);
-    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : 512;
+    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : (sw >= 2048 ? 512u : 256u);
     std::vector<std::pair<uint64_t, uint64_t>> spans;
     uint64_t max_bound = 0, items = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -651,7 +740,7 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     if (items > 0xffffffffull)
         return SIEVE_ERANGE;
     const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + items * sizeof(uint32_t) +
-                               n * sizeof(unsigned long long) + 256;
+                               n * sizeof(unsigned long long) + sizeof(sv::BatchHeader);
     if (dev_bytes > c->hbm_budget)
         return SIEVE_ENOMEM;
 
@@ -659,68 +748,97 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     if (int st = ensure_primes(c, max_bound))
         return st;
     hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-    c->h_iv.resize(n);
-    c->h_item.resize(items);
+    if (int st = grow_host(c, c->s_iv, n * sizeof(sv::BatchInterval)))
+        return st;
+    if (int st = grow_host(c, c->s_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
+        return st;
+    if (int st = grow_host(c, c->s_hdr, sizeof(sv::BatchHeader)))
+        return st;
+    // The staging buffers may still feed the previous call's uploads.
+    HIP_TRY(c, hipStreamSynchronize(s));
+
+    // Intervals whose segments carry the most base primes go first, so the
+    // cheapest work items are the ones left at the end of the queue.
+    sv::BatchInterval *h_iv = static_cast<sv::BatchInterval *>(c->s_iv.p);
+    uint32_t *h_item = static_cast<uint32_t *>(c->s_item.p);
+    c->order.resize(n);
+    std::vector<uint32_t> nmark(n), ndense(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        marking_primes(c, iv[i].hi >= 2 ? isqrt_u64(iv[i].hi - 1) : 0, dense_limit, &nmark[i], &ndense[i]);
+        c->order[i] = i;
+    }
+    std::stable_sort(c->order.begin(), c->order.end(),
+                     [&](uint32_t a, uint32_t b) { return nmark[a] > nmark[b]; });
     uint32_t next = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        sv::BatchInterval &b = c->h_iv[i];
+        sv::BatchInterval &b = h_iv[i];
         const uint64_t lo = iv[i].lo, hi = iv[i].hi;
         b.first_odd = (lo & ~1ull) + 1;
         b.nbits = hi / 2 - lo / 2;
         b.n_words = (b.nbits + 31) / 32;
         b.word_offset = (iv[i].flags & SIEVE_WANT_BITMAP) ? iv[i].word_offset : ~0ull;
-        uint32_t nm = 0, nd = 0;
-        marking_primes(c, hi >= 2 ? isqrt_u64(hi - 1) : 0, dense_limit, &nm, &nd);
-        b.n_primes = nm;
-        b.n_dense = nd;
-        b.seg_begin = next;
+        b.n_primes = nmark[i];
+        b.n_dense = ndense[i];
         b.pad = 0;
-        const uint32_t segs = static_cast<uint32_t>((b.n_words + sw - 1) / sw);
+    }
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint32_t i = c->order[j];
+        const uint32_t segs = static_cast<uint32_t>((h_iv[i].n_words + sw - 1) / sw);
+        h_iv[i].seg_begin = next;
         for (uint32_t k = 0; k < segs; ++k)
-            c->h_item[next + k] = i;
+            h_item[next + k] = i;
         next += segs;
     }
+    sv::BatchHeader *h_hdr = static_cast<sv::BatchHeader *>(c->s_hdr.p);
+    h_hdr->n_intervals = n;
+    h_hdr->n_items = static_cast<uint32_t>(items);
+    h_hdr->queue = 0;
+    h_hdr->pad = 0;
+
     if (int st = grow(c, c->b_iv, n * sizeof(sv::BatchInterval)))
         return st;
     if (int st = grow(c, c->b_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
         return st;
     if (int st = grow(c, c->b_counts, n * sizeof(unsigned long long)))
         return st;
-    if (int st = grow(c, c->b_queue, 256))
+    if (int st = grow(c, c->b_hdr, sizeof(sv::BatchHeader)))
         return st;
-    if (c->h_counts_cap < n) {
-        if (c->h_counts)
-            HIP_TRY(c, hipHostFree(c->h_counts));
-        c->h_counts = nullptr;
-        c->h_counts_cap = 0;
-        HIP_TRY(c, hipHostMalloc(&c->h_counts, n * sizeof(unsigned long long), hipHostMallocDefault));
-        c->h_counts_cap = n;
-    }
-    HIP_TRY(c, hipMemcpyAsync(c->b_iv.p, c->h_iv.data(), n * sizeof(sv::BatchInterval),
-                              hipMemcpyHostToDevice, s));
-    if (items)
-        HIP_TRY(c, hipMemcpyAsync(c->b_item.p, c->h_item.data(), items * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemsetAsync(c->b_counts.p, 0, n * sizeof(unsigned long long), s));
-    HIP_TRY(c, hipMemsetAsync(c->b_queue.p, 0, sizeof(uint32_t), s));
+    if (int st = grow_host(c, c->s_counts, c->b_counts.bytes))
+        return st;
     uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(sw, threads));
     if (c->tuning.wg_per_cu)
         per_cu = std::min(per_cu, c->tuning.wg_per_cu);
-    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(items, uint64_t(per_cu) * c->n_cu));
+    GraphKey k{};
+    k.iv = c->b_iv.p;
+    k.item = c->b_item.p;
+    k.hdr = c->b_hdr.p;
+    k.counts = c->b_counts.p;
+    k.h_counts = c->s_counts.p;
+    k.primes = c->d_primes + sv::kPresievePrimes;
+    k.inv = c->d_inv + sv::kPresievePrimes;
+    k.words = d_words;
+    k.seg_words = sw;
+    k.threads = threads;
+    k.blocks = per_cu * c->n_cu;
+    k.max_intervals = static_cast<uint32_t>(c->b_counts.bytes / sizeof(unsigned long long));
+    k.counts_bytes = c->b_counts.bytes;
+    if (!c->graph_exec || !(c->graph_key == k))
+        if (int st = capture_batch_graph(c, k))
+            return st;
+    HIP_TRY(c, hipMemcpyAsync(c->b_iv.p, h_iv, n * sizeof(sv::BatchInterval), hipMemcpyHostToDevice, s));
+    if (items)
+        HIP_TRY(c, hipMemcpyAsync(c->b_item.p, h_item, items * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->b_hdr.p, h_hdr, sizeof(sv::BatchHeader), hipMemcpyHostToDevice, s));
+
     c->ev_valid = false;
     HIP_TRY(c, hipEventRecord(c->ev_start, s));
-    HIP_TRY(c, sv::launch_batch(static_cast<const sv::BatchInterval *>(c->b_iv.p), n,
-                                static_cast<const uint32_t *>(c->b_item.p), static_cast<uint32_t>(items),
-                                c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, d_words,
-                                static_cast<unsigned long long *>(c->b_counts.p),
-                                static_cast<uint32_t *>(c->b_queue.p), sw, threads, blocks, s));
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
     HIP_TRY(c, hipEventRecord(c->ev_stop, s));
     c->ev_valid = true;
-    HIP_TRY(c, hipMemcpyAsync(c->h_counts, c->b_counts.p, n * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    const unsigned long long *h_counts = static_cast<const unsigned long long *>(c->s_counts.p);
     for (uint32_t i = 0; i < n; ++i)
-        pi_out[i] = c->h_counts[i] + ((iv[i].lo <= 2 && 2 < iv[i].hi) ? 1 : 0);
+        pi_out[i] = h_counts[i] + ((iv[i].lo <= 2 && 2 < iv[i].hi) ? 1 : 0);
     return SIEVE_OK;
 }
 

@@ -49,6 +49,14 @@ struct BatchInterval {
     uint32_t pad;
 };
 
+// Sizes and work counter of a batch launch, in device memory.
+struct BatchHeader {
+    uint32_t n_intervals;
+    uint32_t n_items;
+    uint32_t queue;  // next item; zeroed by the reset kernel
+    uint32_t pad;
+};
+
 // Launchers (sieve_kernels.hip).  All return the first HIP error.
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
 
@@ -66,10 +74,12 @@ uint64_t compact_tmp_words(uint64_t n_words);
 hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t first_odd,
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
 
-hipError_t launch_batch(const BatchInterval *d_iv, uint32_t n_iv, const uint32_t *d_item_iv,
-                        uint32_t n_items, const uint32_t *d_primes, const double *d_inv,
-                        uint32_t *d_words,
-                        unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
+// Reset kernel (counts[0 .. n_intervals) and the queue) followed by the
+// persistent batch kernel; both read their sizes from d_hdr.  max_intervals
+// sizes the reset grid.
+hipError_t launch_batch(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
+                        uint32_t max_intervals, const uint32_t *d_primes, const double *d_inv,
+                        uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
 
 // The segment kernels are built for a few static LDS sizes: the smallest

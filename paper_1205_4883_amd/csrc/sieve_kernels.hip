@@ -365,25 +365,26 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     }
 }
 
-// Persistent batch kernel: workgroups pop (interval, segment) items from a
-// device counter until the queue is empty.  Every workgroup leaves the loop
-// once the counter passes n_items, so the grid always drains.
+// Persistent batch kernel: workgroups pop (interval, segment) items from the
+// header's counter until the queue is empty (hdr->n_items items).  Every
+// workgroup leaves the loop once the counter passes n_items, so the grid
+// always drains.  All sizes are read from device memory, so one captured
+// graph serves batches of any size up to its buffers' capacity.
 template <uint32_t kSegMax>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(const BatchInterval *ivs, const uint32_t *item_iv,
-                                                      uint32_t n_items, const uint32_t *primes,
-                                                      const double *inv, uint32_t *words,
-                                                      unsigned long long *counts, uint32_t *queue,
-                                                      uint32_t seg_words)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(
+    const BatchInterval *ivs, const uint32_t *item_iv, BatchHeader *hdr, const uint32_t *primes,
+    const double *inv, uint32_t *words, unsigned long long *counts, uint32_t seg_words)
 {
     __shared__ uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
+    const uint32_t n_items = hdr->n_items;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
-            item_sh = atomicAdd(queue, 1u);
+            item_sh = atomicAdd(&hdr->queue, 1u);
         __syncthreads();
         const uint32_t item = item_sh;
         if (item >= n_items)
@@ -398,6 +399,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             sieve_segment<false>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes,
                                  inv, iv.n_dense, iv.n_primes, nullptr, counts + k);
     }
+}
+
+// Zero the per-interval counts and the work counter of a batch (a kernel, not
+// a memset, so that it can sit in a captured graph).
+__global__ void __launch_bounds__(256) batch_reset_kernel(BatchHeader *hdr, unsigned long long *counts)
+{
+    const uint32_t n = hdr->n_intervals;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        counts[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        hdr->queue = 0;
 }
 
 // Odd integers below 2^16 in one workgroup: bit i of bits[] is 2i + 1,
@@ -604,13 +616,13 @@ void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words
 }
 
 template <uint32_t kSegMax>
-void launch_batch_cap(const BatchInterval *d_iv, const uint32_t *d_item_iv, uint32_t n_items,
+void launch_batch_cap(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
                       const uint32_t *d_primes, const double *d_inv, uint32_t *d_words,
-                      unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
-                      uint32_t threads, uint32_t grid, hipStream_t s)
+                      unsigned long long *d_counts, uint32_t seg_words, uint32_t threads, uint32_t grid,
+                      hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_iv, d_item_iv, n_items,
-                       d_primes, d_inv, d_words, d_counts, d_queue, seg_words);
+    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_iv, d_item_iv, d_hdr,
+                       d_primes, d_inv, d_words, d_counts, seg_words);
 }
 }  // namespace
 
@@ -685,20 +697,22 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchInterval *d_iv, uint32_t n_iv, const uint32_t *d_item_iv,
-                        uint32_t n_items, const uint32_t *d_primes, const double *d_inv, uint32_t *d_words,
-                        unsigned long long *d_counts, uint32_t *d_queue, uint32_t seg_words,
+hipError_t launch_batch(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
+                        uint32_t max_intervals, const uint32_t *d_primes, const double *d_inv,
+                        uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_blocks, hipStream_t s)
 {
-    (void)n_iv;
-    if (n_items == 0 || n_blocks == 0)
+    if (n_blocks == 0)
         return hipSuccess;
+    const uint32_t reset_blocks = (max_intervals + 255) / 256 > 0 ? (max_intervals + 255) / 256 : 1;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(reset_blocks < 1024 ? reset_blocks : 1024), dim3(256), 0, s,
+                       d_hdr, d_counts);
     switch (seg_capacity_for(seg_words)) {
-    case 512: launch_batch_cap<512>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
-    case 2048: launch_batch_cap<2048>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
-    case 8192: launch_batch_cap<8192>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
-    case 16384: launch_batch_cap<16384>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
-    case 32768: launch_batch_cap<32768>(d_iv, d_item_iv, n_items, d_primes, d_inv, d_words, d_counts, d_queue, seg_words, block_threads, n_blocks, s); break;
+    case 512: launch_batch_cap<512>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 2048: launch_batch_cap<2048>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 8192: launch_batch_cap<8192>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 16384: launch_batch_cap<16384>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 32768: launch_batch_cap<32768>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

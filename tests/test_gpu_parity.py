@@ -265,3 +265,45 @@ def test_async_bitmaps_on_several_streams(gpu, oracle_mod, sv_mod):
     for (lo, hi), (out, _) in zip(ranges, outs):
         ref, _ = oracle_mod.bitmap(lo, hi)
         assert np.array_equal(out.cpu().numpy().view(np.uint32)[:ref.size], ref), (lo, hi)
+
+
+def test_batch_graph_replays_and_shrinks(gpu, oracle_mod):
+    # the captured batch graph is replayed for batches of different sizes
+    # (it reads sizes from device memory) and must match the oracle each time
+    rng = np.random.default_rng(9)
+    for n in [64, 17, 64, 1]:
+        los = np.floor(np.exp(rng.uniform(np.log(10), np.log(1e12), n))).astype(np.uint64)
+        his = los + np.floor(np.exp(rng.uniform(0, np.log(2e6), n))).astype(np.uint64)
+        pi = gpu.batch(los, his, want_bitmap=False)
+        for i in range(n):
+            assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), (n, i)
+
+
+@pytest.mark.parametrize("seg_bits,threads", [(4096, 256), (65536, 256), (1048576, 1024)])
+def test_batch_tunings(gpu, oracle_mod, seg_bits, threads):
+    rng = np.random.default_rng(seg_bits)
+    los = np.floor(np.exp(rng.uniform(0, np.log(1e11), 40))).astype(np.uint64)
+    his = los + np.floor(np.exp(rng.uniform(0, np.log(3e6), 40))).astype(np.uint64)
+    gpu.tuning(seg_bits=seg_bits, block_threads=threads)
+    try:
+        pi, words, offs = gpu.batch(los, his, want_bitmap=True)
+        host = words.cpu().numpy().view(np.uint32)
+        for i in range(len(los)):
+            ref, ref_pi = oracle_mod.bitmap(int(los[i]), int(his[i]))
+            assert int(pi[i]) == ref_pi
+            o = int(offs[i])
+            assert np.array_equal(host[o:o + ref.size], ref), i
+    finally:
+        gpu.tuning()
+        gpu.tuning(seg_bits=0, block_threads=0)
+
+
+def test_batch_workload_counts(gpu, oracle_mod):
+    # the full 4096-interval batched workload: every count against the oracle
+    from paper_1205_4883_amd import workloads
+
+    los, his = workloads.batch_intervals(0)
+    print("case batch workload seed 0", flush=True)
+    pi = gpu.batch(los, his, want_bitmap=False)
+    for i in range(len(los)):
+        assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), i
