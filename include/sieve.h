@@ -190,6 +190,98 @@ typedef struct sieve_interval {
 SIEVE_API int sieve_batch(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                 uint64_t total_words, uint64_t *pi_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * A server owns its own context on one device and a dispatcher thread.
+ * Requests (ranges) are admitted in arrival order while the device bytes
+ * they hold (their bitmaps) fit the HBM budget and their returned bitmaps fit
+ * the pinned host arena; admitted requests are packed into batches (the
+ * sieve_batch work queue) on up to `lanes` streams at once, so requests that
+ * arrive while others run are batched and overlap on the device.  Results
+ * are identical to sieving each range alone.
+ * ---------------------------------------------------------------------- */
+typedef struct sieve_server sieve_server;
+
+#define SIEVE_SERVE_BATCHED 0u /* continuous batching over several lanes */
+#define SIEVE_SERVE_PLAIN 1u   /* one request at a time, plain launches */
+
+/* A zero field means the default in brackets. */
+typedef struct sieve_server_config {
+    uint32_t lanes;            /* batches in flight at once, one stream each [3] */
+    uint32_t max_batch;        /* requests per batch [1024] */
+    uint64_t max_batch_words;  /* bitmap words per batch: each lane's device
+                                  output buffer [2^26 = 256 MiB] */
+    uint64_t hbm_budget_bytes; /* device bytes admitted requests may hold [32 GiB] */
+    uint64_t host_arena_bytes; /* pinned host memory for returned bitmaps [2 GiB] */
+    uint32_t mode;             /* SIEVE_SERVE_BATCHED or SIEVE_SERVE_PLAIN */
+    uint32_t pad;
+} sieve_server_config;
+
+/* A finished request.  words points into the server's pinned host arena
+ * (flags & SIEVE_WANT_BITMAP) and stays valid until sieve_server_release.
+ * Times are steady-clock nanoseconds. */
+typedef struct sieve_result {
+    uint64_t id;
+    uint64_t lo;
+    uint64_t hi;
+    uint64_t pi;
+    const uint32_t *words;
+    uint64_t n_words;
+    uint64_t t_submit_ns;
+    uint64_t t_admit_ns;
+    uint64_t t_launch_ns;
+    uint64_t t_done_ns;
+    int32_t status;
+    uint32_t flags;
+} sieve_result;
+
+typedef struct sieve_server_stats {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t batches;           /* batches (or plain launches) issued */
+    uint64_t max_batch_seen;    /* most requests in one batch */
+    uint64_t max_inflight;      /* most batches on the device at once */
+    uint64_t deferred;          /* admissions that had to wait for budget */
+    uint64_t peak_admitted_bytes;
+} sieve_server_stats;
+
+/* Start a server on HIP device hip_device (cfg NULL = defaults).  Errors:
+ * SIEVE_EINVAL, SIEVE_ENODEV, SIEVE_ENOMEM, SIEVE_EDEVICE. */
+SIEVE_API int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_server **out);
+
+/* Queue the range [lo, hi); flags: SIEVE_WANT_BITMAP to get its bitmap back.
+ * Returns at once with the request id.  Errors: SIEVE_EINVAL (lo > hi, NULL
+ * id_out), SIEVE_ERANGE (hi > SIEVE_MAX_HI), SIEVE_ENOMEM (the request alone
+ * exceeds a budget or the lane buffer). */
+SIEVE_API int sieve_server_submit(sieve_server *s, uint64_t lo, uint64_t hi, uint32_t flags,
+                                  uint64_t *id_out);
+
+/* Move up to max finished results into out[0 .. *n_out), waiting up to
+ * wait_us microseconds for the first one. */
+SIEVE_API int sieve_server_poll(sieve_server *s, sieve_result *out, uint32_t max, uint32_t *n_out,
+                                uint32_t wait_us);
+
+/* Return a finished bitmap request's host buffer to the arena.  Results
+ * without a bitmap need no release.  SIEVE_EINVAL for an unknown id. */
+SIEVE_API int sieve_server_release(sieve_server *s, uint64_t id);
+
+SIEVE_API int sieve_server_get_stats(sieve_server *s, sieve_server_stats *out);
+
+/* Finish every submitted request, stop the dispatcher and free everything
+ * (unreleased result buffers included).  NULL is ignored. */
+SIEVE_API int sieve_server_destroy(sieve_server *s);
+
+/* Replay a timed trace through a server: request i (lo[i], hi[i],
+ * flags[i]) is submitted at t_arrival_s[i] seconds after the start by a
+ * native submitter thread; results are released as they arrive.  Fills
+ * pi_out[i] and latency_ms_out[i] (arrival to result on the host), and
+ * stats_out if not NULL. */
+SIEVE_API int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint64_t *lo,
+                                const uint64_t *hi, const uint32_t *flags, const double *t_arrival_s,
+                                uint64_t n, uint64_t *pi_out, double *latency_ms_out,
+                                sieve_server_stats *stats_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,8 +8,17 @@ from .sieve import (  # noqa: F401
     INTERVAL_DTYPE,
     LIB_PATH,
     SIEVE_MAX_HI,
+    Server,
     Sieve,
     SieveError,
+    result_words,
+    sieve_serve_trace,
+    sieve_server_create,
+    sieve_server_destroy,
+    sieve_server_get_stats,
+    sieve_server_poll,
+    sieve_server_release,
+    sieve_server_submit,
     sieve_base_primes,
     sieve_batch,
     sieve_bitmap_words,

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsieve.so")
-SOURCES = ["sieve_kernels.hip", "sieve_api.hip"]
+SOURCES = ["sieve_kernels.hip", "sieve_api.hip", "sieve_serve.hip"]
 
 
 def hipcc_command(out):
@@ -21,7 +21,7 @@ def hipcc_command(out):
         "-Wno-pass-failed",
         # never let the compiler form packed fp32 ops
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-I", INCLUDE, "-I", CSRC,
+        "-I", INCLUDE, "-I", CSRC, "-pthread",
         *[os.path.join(CSRC, s) for s in SOURCES],
         "-o", out,
     ]

@@ -10,96 +10,11 @@
 #include <new>
 #include <vector>
 
-#include "sieve.h"
-#include "sieve_internal.h"
+#include "sieve_runtime.h"
 
-namespace {
+namespace sv {
 
-constexpr uint64_t kMaxPrimeLimit = 31622777;      // > isqrt(SIEVE_MAX_HI)
-constexpr uint64_t kDefaultPrimeLimit = 1u << 20;  // covers hi <= 1.0995e12
-constexpr uint32_t kSegGranuleWords = 128;         // 4096 bits
-constexpr uint32_t kDefaultMaxSegWords = 16384;    // 2^19 bits = 64 KiB of LDS
-constexpr uint64_t kDefaultBudget = 32ull << 30;
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct HostBuf {  // pinned host memory
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-// Everything a captured batch graph bakes in.
-struct GraphKey {
-    const void *iv, *item, *hdr, *counts, *h_counts, *primes, *inv;
-    uint32_t *words;
-    uint32_t seg_words, threads, blocks, max_intervals;
-    size_t counts_bytes;
-    bool operator==(const GraphKey &o) const
-    {
-        return iv == o.iv && item == o.item && hdr == o.hdr && counts == o.counts &&
-               h_counts == o.h_counts && primes == o.primes && inv == o.inv && words == o.words &&
-               seg_words == o.seg_words && threads == o.threads && blocks == o.blocks &&
-               max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
-    }
-};
-
-}  // namespace
-
-struct sieve_ctx {
-    int device = 0;
-    uint32_t n_cu = 0;
-    uint32_t lds_max = 0;  // LDS bytes one workgroup may use
-    uint32_t lds_per_cu = 0;
-    uint64_t hbm_budget = kDefaultBudget;
-    hipStream_t stream = nullptr;
-    sieve_tuning tuning{};
-    int last_hip = 0;
-
-    // base primes: all odd primes <= primes_limit, ascending
-    uint64_t primes_limit = 0;
-    std::vector<uint32_t> h_primes;
-    uint32_t *d_primes = nullptr;
-    double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
-
-    // Per-call device words {count, segment queue}: kSlots slots used in
-    // turn, each guarded by an event so that an asynchronous call still
-    // running on another stream never sees its slot reset.
-    static constexpr int kSlots = 16;
-    unsigned long long *d_count = nullptr;  // 2 * kSlots words
-    hipEvent_t slot_done[kSlots] = {};
-    bool slot_used[kSlots] = {};
-    int next_slot = 0;
-    unsigned long long *h_count = nullptr;  // pinned
-
-    // events bracketing the last sieve kernel launch (range or batch)
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-    bool ev_valid = false;
-
-    // batch buffers, grown on demand; host staging is pinned so that the
-    // uploads are asynchronous
-    DevBuf b_iv, b_item, b_counts, b_hdr;
-    HostBuf s_iv, s_item, s_counts, s_hdr;
-    std::vector<uint32_t> order;
-
-    // the captured batch graph (reset kernel, batch kernel, count readback)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    GraphKey graph_key{};
-};
-
-namespace {
-
-#define HIP_TRY(ctx, expr)                    \
-    do {                                      \
-        hipError_t e_ = (expr);               \
-        if (e_ != hipSuccess) {               \
-            (ctx)->last_hip = static_cast<int>(e_); \
-            return SIEVE_EDEVICE;             \
-        }                                     \
-    } while (0)
+#define HIP_TRY SV_HIP_TRY
 
 uint64_t isqrt_u64(uint64_t n)
 {
@@ -310,7 +225,14 @@ int build_primes(sieve_ctx *c, uint64_t limit)
             st = SIEVE_EDEVICE;
             break;
         }
-        // the bitmap of [0, limit] has no bit for 2: the list is the odd primes
+        // the bitmap of [0, limit] has no bit for 2: the list is the odd primes.
+        // Launches on other streams may still read the old table.
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            st = SIEVE_EDEVICE;
+            break;
+        }
         if (c->d_primes)
             (void)hipFree(c->d_primes);
         if (c->d_inv)
@@ -442,21 +364,23 @@ int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes)
     return SIEVE_OK;
 }
 
-void drop_graph(sieve_ctx *c)
+namespace {
+
+void drop_graph(BatchEngine &e)
 {
-    if (c->graph_exec)
-        (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph)
-        (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+    if (e.exec)
+        (void)hipGraphExecDestroy(e.exec);
+    if (e.graph)
+        (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
 }
 
 // Capture the batch launch sequence on the context's own stream (capture runs
 // nothing) and instantiate it; the graph may then be launched on any stream.
-int capture_batch_graph(sieve_ctx *c, const GraphKey &k)
+int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
 {
-    drop_graph(c);
+    drop_graph(eng);
     hipStream_t cs = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = sv::launch_batch(static_cast<const sv::BatchInterval *>(k.iv),
@@ -474,16 +398,192 @@ int capture_batch_graph(sieve_ctx *c, const GraphKey &k)
     if (e == hipSuccess)
         e = e2;
     if (e == hipSuccess)
-        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&eng.exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         if (g)
             (void)hipGraphDestroy(g);
-        c->graph_exec = nullptr;
+        eng.exec = nullptr;
         c->last_hip = e;
         return SIEVE_EDEVICE;
     }
-    c->graph = g;
-    c->graph_key = k;
+    eng.graph = g;
+    eng.key = k;
+    return SIEVE_OK;
+}
+
+}  // namespace
+
+int engine_init(sieve_ctx *c, BatchEngine &e)
+{
+    HIP_TRY(c, hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
+    return SIEVE_OK;
+}
+
+void engine_free(BatchEngine &e)
+{
+    if (e.done && e.pending)
+        (void)hipEventSynchronize(e.done);
+    drop_graph(e);
+    for (DevBuf *b : {&e.iv, &e.item, &e.counts, &e.hdr})
+        if (b->p)
+            (void)hipFree(b->p);
+    for (HostBuf *b : {&e.s_iv, &e.s_item, &e.s_counts, &e.s_hdr})
+        if (b->p)
+            (void)hipHostFree(b->p);
+    if (e.done)
+        (void)hipEventDestroy(e.done);
+    e = BatchEngine();
+}
+
+int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
+                 uint64_t total_words)
+{
+    if (int st = validate_tuning(c->tuning, c->lds_max))
+        return st;
+    const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
+    const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
+    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
+                                          sv::kFirstMarkedPrime);
+    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : (sw >= 2048 ? 512u : 256u);
+    std::vector<std::pair<uint64_t, uint64_t>> spans;
+    uint64_t max_bound = 0, items = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (iv[i].lo > iv[i].hi)
+            return SIEVE_EINVAL;
+        if (iv[i].hi > SIEVE_MAX_HI)
+            return SIEVE_ERANGE;
+        const uint64_t nw = sieve_bitmap_words(iv[i].lo, iv[i].hi);
+        if (iv[i].flags & SIEVE_WANT_BITMAP) {
+            if (nw && !d_words)
+                return SIEVE_EINVAL;
+            if (iv[i].word_offset > total_words || nw > total_words - iv[i].word_offset)
+                return SIEVE_EBUFSZ;
+            if (nw)
+                spans.emplace_back(iv[i].word_offset, iv[i].word_offset + nw);
+        }
+        if (iv[i].hi >= 2)
+            max_bound = std::max(max_bound, isqrt_u64(iv[i].hi - 1));
+        items += (nw + sw - 1) / sw;
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second)
+            return SIEVE_EINVAL;
+    if (items > 0xffffffffull)
+        return SIEVE_ERANGE;
+    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + items * sizeof(uint32_t) +
+                               n * sizeof(unsigned long long) + sizeof(sv::BatchHeader);
+    if (dev_bytes > c->hbm_budget)
+        return SIEVE_ENOMEM;
+
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = ensure_primes(c, max_bound))
+        return st;
+    // The staging buffers may still feed the previous launch's uploads.
+    if (e.pending)
+        HIP_TRY(c, hipEventSynchronize(e.done));
+    e.pending = false;
+    if (int st = grow_host(c, e.s_iv, std::max<uint64_t>(1, n) * sizeof(sv::BatchInterval)))
+        return st;
+    if (int st = grow_host(c, e.s_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
+        return st;
+    if (int st = grow_host(c, e.s_hdr, sizeof(sv::BatchHeader)))
+        return st;
+
+    // Intervals whose segments carry the most base primes go first, so the
+    // cheapest work items are the ones left at the end of the queue.
+    sv::BatchInterval *h_iv = static_cast<sv::BatchInterval *>(e.s_iv.p);
+    uint32_t *h_item = static_cast<uint32_t *>(e.s_item.p);
+    e.order.resize(n);
+    e.nmark.resize(n);
+    e.ndense.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        marking_primes(c, iv[i].hi >= 2 ? isqrt_u64(iv[i].hi - 1) : 0, dense_limit, &e.nmark[i], &e.ndense[i]);
+        e.order[i] = i;
+    }
+    std::stable_sort(e.order.begin(), e.order.end(),
+                     [&](uint32_t a, uint32_t b) { return e.nmark[a] > e.nmark[b]; });
+    for (uint32_t i = 0; i < n; ++i) {
+        sv::BatchInterval &b = h_iv[i];
+        const uint64_t lo = iv[i].lo, hi = iv[i].hi;
+        b.first_odd = (lo & ~1ull) + 1;
+        b.nbits = hi / 2 - lo / 2;
+        b.n_words = (b.nbits + 31) / 32;
+        b.word_offset = (iv[i].flags & SIEVE_WANT_BITMAP) ? iv[i].word_offset : ~0ull;
+        b.n_primes = e.nmark[i];
+        b.n_dense = e.ndense[i];
+        b.pad = 0;
+    }
+    uint32_t next = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint32_t i = e.order[j];
+        const uint32_t segs = static_cast<uint32_t>((h_iv[i].n_words + sw - 1) / sw);
+        h_iv[i].seg_begin = next;
+        for (uint32_t k = 0; k < segs; ++k)
+            h_item[next + k] = i;
+        next += segs;
+    }
+    sv::BatchHeader *h_hdr = static_cast<sv::BatchHeader *>(e.s_hdr.p);
+    h_hdr->n_intervals = n;
+    h_hdr->n_items = static_cast<uint32_t>(items);
+    h_hdr->queue = 0;
+    h_hdr->pad = 0;
+    e.n = n;
+    e.items = items;
+    e.seg_words = sw;
+    e.dense_limit = dense_limit;
+    e.threads = threads;
+    return SIEVE_OK;
+}
+
+int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed)
+{
+    const uint32_t n = e.n;
+    if (int st = grow(c, e.iv, std::max<uint64_t>(1, n) * sizeof(sv::BatchInterval)))
+        return st;
+    if (int st = grow(c, e.item, std::max<uint64_t>(1, e.items) * sizeof(uint32_t)))
+        return st;
+    if (int st = grow(c, e.counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long)))
+        return st;
+    if (int st = grow(c, e.hdr, sizeof(sv::BatchHeader)))
+        return st;
+    if (int st = grow_host(c, e.s_counts, e.counts.bytes))
+        return st;
+    uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(e.seg_words, e.threads));
+    if (c->tuning.wg_per_cu)
+        per_cu = std::min(per_cu, c->tuning.wg_per_cu);
+    GraphKey k{};
+    k.iv = e.iv.p;
+    k.item = e.item.p;
+    k.hdr = e.hdr.p;
+    k.counts = e.counts.p;
+    k.h_counts = e.s_counts.p;
+    k.primes = c->d_primes + sv::kPresievePrimes;
+    k.inv = c->d_inv + sv::kPresievePrimes;
+    k.words = d_words;
+    k.seg_words = e.seg_words;
+    k.threads = e.threads;
+    k.blocks = per_cu * c->n_cu;
+    k.max_intervals = static_cast<uint32_t>(e.counts.bytes / sizeof(unsigned long long));
+    k.counts_bytes = e.counts.bytes;
+    if (!e.exec || !(e.key == k))
+        if (int st = capture_batch_graph(c, e, k))
+            return st;
+    HIP_TRY(c, hipMemcpyAsync(e.iv.p, e.s_iv.p, n * sizeof(sv::BatchInterval), hipMemcpyHostToDevice, s));
+    if (e.items)
+        HIP_TRY(c, hipMemcpyAsync(e.item.p, e.s_item.p, e.items * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(e.hdr.p, e.s_hdr.p, sizeof(sv::BatchHeader), hipMemcpyHostToDevice, s));
+    if (timed) {
+        c->ev_valid = false;
+        HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    }
+    HIP_TRY(c, hipGraphLaunch(e.exec, s));
+    if (timed) {
+        HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+        c->ev_valid = true;
+    }
+    HIP_TRY(c, hipEventRecord(e.done, s));
+    e.pending = true;
     return SIEVE_OK;
 }
 
@@ -516,7 +616,7 @@ uint64_t sieve_bitmap_words(uint64_t lo, uint64_t hi)
 int sieve_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tuning, uint32_t n_cu, uint32_t lds_bytes,
                sieve_plan_info *out)
 {
-    return make_plan(lo, hi, tuning, n_cu, lds_bytes, out);
+    return sv::make_plan(lo, hi, tuning, n_cu, lds_bytes, out);
 }
 
 int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
@@ -561,7 +661,9 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
         st = SIEVE_EDEVICE;
     }
     if (st == SIEVE_OK)
-        st = ensure_primes(c, kDefaultPrimeLimit);
+        st = sv::engine_init(c, c->batch);
+    if (st == SIEVE_OK)
+        st = sv::ensure_primes(c, sv::kDefaultPrimeLimit);
     if (st != SIEVE_OK) {
         sieve_destroy(c);
         return st;
@@ -577,13 +679,7 @@ int sieve_destroy(sieve_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
-    drop_graph(c);
-    for (DevBuf *b : {&c->b_iv, &c->b_item, &c->b_counts, &c->b_hdr})
-        if (b->p)
-            (void)hipFree(b->p);
-    for (HostBuf *b : {&c->s_iv, &c->s_item, &c->s_counts, &c->s_hdr})
-        if (b->p)
-            (void)hipHostFree(b->p);
+    sv::engine_free(c->batch);
     if (c->d_primes)
         (void)hipFree(c->d_primes);
     if (c->d_inv)
@@ -614,10 +710,10 @@ int sieve_last_kernel_ms(sieve_ctx *c, double *ms)
 {
     if (!c || !ms || !c->ev_valid)
         return SIEVE_EINVAL;
-    HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipEventSynchronize(c->ev_stop));
+    SV_HIP_TRY(c, hipSetDevice(c->device));
+    SV_HIP_TRY(c, hipEventSynchronize(c->ev_stop));
     float f = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&f, c->ev_start, c->ev_stop));
+    SV_HIP_TRY(c, hipEventElapsedTime(&f, c->ev_start, c->ev_stop));
     *ms = f;
     return SIEVE_OK;
 }
@@ -634,7 +730,7 @@ int sieve_set_tuning(sieve_ctx *c, const sieve_tuning *t)
 {
     if (!c || !t)
         return SIEVE_EINVAL;
-    if (int st = validate_tuning(*t, c->lds_max))
+    if (int st = sv::validate_tuning(*t, c->lds_max))
         return st;
     c->tuning = *t;
     return SIEVE_OK;
@@ -644,10 +740,10 @@ int sieve_base_primes(sieve_ctx *c, uint64_t limit, uint32_t *out, uint64_t cap,
 {
     if (!c || !n_out)
         return SIEVE_EINVAL;
-    if (limit > kMaxPrimeLimit)
+    if (limit > sv::kMaxPrimeLimit)
         return SIEVE_ERANGE;
-    HIP_TRY(c, hipSetDevice(c->device));
-    if (int st = ensure_primes(c, limit))
+    SV_HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = sv::ensure_primes(c, limit))
         return st;
     const auto &v = c->h_primes;
     const uint64_t n_odd = static_cast<uint64_t>(std::upper_bound(v.begin(), v.end(), limit) - v.begin());
@@ -675,7 +771,7 @@ int sieve_range_count(sieve_ctx *c, uint64_t lo, uint64_t hi, uint64_t *pi_out, 
     if (hi > SIEVE_MAX_HI)
         return SIEVE_ERANGE;
     hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-    return run_range(c, lo, hi, nullptr, pi_out, s);
+    return sv::run_range(c, lo, hi, nullptr, pi_out, s);
 }
 
 int sieve_range_bitmap(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t n_words,
@@ -693,7 +789,7 @@ int sieve_range_bitmap(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words
     if (n_words < need)
         return SIEVE_EBUFSZ;
     hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-    return run_range(c, lo, hi, d_words, pi_out, s);
+    return sv::run_range(c, lo, hi, d_words, pi_out, s);
 }
 
 int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
@@ -705,138 +801,14 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
         return SIEVE_EINVAL;
     if (n == 0)
         return SIEVE_OK;
-    // validate every interval before any device work
-    if (int st = validate_tuning(c->tuning, c->lds_max))
-        return st;
-    const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
-    const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
-    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
-                                          sv::kFirstMarkedPrime);
-    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : (sw >= 2048 ? 512u : 256u);
-    std::vector<std::pair<uint64_t, uint64_t>> spans;
-    uint64_t max_bound = 0, items = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        if (iv[i].lo > iv[i].hi)
-            return SIEVE_EINVAL;
-        if (iv[i].hi > SIEVE_MAX_HI)
-            return SIEVE_ERANGE;
-        const uint64_t nw = sieve_bitmap_words(iv[i].lo, iv[i].hi);
-        if (iv[i].flags & SIEVE_WANT_BITMAP) {
-            if (nw && !d_words)
-                return SIEVE_EINVAL;
-            if (iv[i].word_offset > total_words || nw > total_words - iv[i].word_offset)
-                return SIEVE_EBUFSZ;
-            if (nw)
-                spans.emplace_back(iv[i].word_offset, iv[i].word_offset + nw);
-        }
-        if (iv[i].hi >= 2)
-            max_bound = std::max(max_bound, isqrt_u64(iv[i].hi - 1));
-        items += (nw + sw - 1) / sw;
-    }
-    std::sort(spans.begin(), spans.end());
-    for (size_t i = 1; i < spans.size(); ++i)
-        if (spans[i].first < spans[i - 1].second)
-            return SIEVE_EINVAL;
-    if (items > 0xffffffffull)
-        return SIEVE_ERANGE;
-    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + items * sizeof(uint32_t) +
-                               n * sizeof(unsigned long long) + sizeof(sv::BatchHeader);
-    if (dev_bytes > c->hbm_budget)
-        return SIEVE_ENOMEM;
-
-    HIP_TRY(c, hipSetDevice(c->device));
-    if (int st = ensure_primes(c, max_bound))
+    if (int st = sv::engine_stage(c, c->batch, iv, n, d_words, total_words))
         return st;
     hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-    if (int st = grow_host(c, c->s_iv, n * sizeof(sv::BatchInterval)))
+    if (int st = sv::engine_launch(c, c->batch, d_words, s, true))
         return st;
-    if (int st = grow_host(c, c->s_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
-        return st;
-    if (int st = grow_host(c, c->s_hdr, sizeof(sv::BatchHeader)))
-        return st;
-    // The staging buffers may still feed the previous call's uploads.
-    HIP_TRY(c, hipStreamSynchronize(s));
-
-    // Intervals whose segments carry the most base primes go first, so the
-    // cheapest work items are the ones left at the end of the queue.
-    sv::BatchInterval *h_iv = static_cast<sv::BatchInterval *>(c->s_iv.p);
-    uint32_t *h_item = static_cast<uint32_t *>(c->s_item.p);
-    c->order.resize(n);
-    std::vector<uint32_t> nmark(n), ndense(n);
-    for (uint32_t i = 0; i < n; ++i) {
-        marking_primes(c, iv[i].hi >= 2 ? isqrt_u64(iv[i].hi - 1) : 0, dense_limit, &nmark[i], &ndense[i]);
-        c->order[i] = i;
-    }
-    std::stable_sort(c->order.begin(), c->order.end(),
-                     [&](uint32_t a, uint32_t b) { return nmark[a] > nmark[b]; });
-    uint32_t next = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        sv::BatchInterval &b = h_iv[i];
-        const uint64_t lo = iv[i].lo, hi = iv[i].hi;
-        b.first_odd = (lo & ~1ull) + 1;
-        b.nbits = hi / 2 - lo / 2;
-        b.n_words = (b.nbits + 31) / 32;
-        b.word_offset = (iv[i].flags & SIEVE_WANT_BITMAP) ? iv[i].word_offset : ~0ull;
-        b.n_primes = nmark[i];
-        b.n_dense = ndense[i];
-        b.pad = 0;
-    }
-    for (uint32_t j = 0; j < n; ++j) {
-        const uint32_t i = c->order[j];
-        const uint32_t segs = static_cast<uint32_t>((h_iv[i].n_words + sw - 1) / sw);
-        h_iv[i].seg_begin = next;
-        for (uint32_t k = 0; k < segs; ++k)
-            h_item[next + k] = i;
-        next += segs;
-    }
-    sv::BatchHeader *h_hdr = static_cast<sv::BatchHeader *>(c->s_hdr.p);
-    h_hdr->n_intervals = n;
-    h_hdr->n_items = static_cast<uint32_t>(items);
-    h_hdr->queue = 0;
-    h_hdr->pad = 0;
-
-    if (int st = grow(c, c->b_iv, n * sizeof(sv::BatchInterval)))
-        return st;
-    if (int st = grow(c, c->b_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
-        return st;
-    if (int st = grow(c, c->b_counts, n * sizeof(unsigned long long)))
-        return st;
-    if (int st = grow(c, c->b_hdr, sizeof(sv::BatchHeader)))
-        return st;
-    if (int st = grow_host(c, c->s_counts, c->b_counts.bytes))
-        return st;
-    uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(sw, threads));
-    if (c->tuning.wg_per_cu)
-        per_cu = std::min(per_cu, c->tuning.wg_per_cu);
-    GraphKey k{};
-    k.iv = c->b_iv.p;
-    k.item = c->b_item.p;
-    k.hdr = c->b_hdr.p;
-    k.counts = c->b_counts.p;
-    k.h_counts = c->s_counts.p;
-    k.primes = c->d_primes + sv::kPresievePrimes;
-    k.inv = c->d_inv + sv::kPresievePrimes;
-    k.words = d_words;
-    k.seg_words = sw;
-    k.threads = threads;
-    k.blocks = per_cu * c->n_cu;
-    k.max_intervals = static_cast<uint32_t>(c->b_counts.bytes / sizeof(unsigned long long));
-    k.counts_bytes = c->b_counts.bytes;
-    if (!c->graph_exec || !(c->graph_key == k))
-        if (int st = capture_batch_graph(c, k))
-            return st;
-    HIP_TRY(c, hipMemcpyAsync(c->b_iv.p, h_iv, n * sizeof(sv::BatchInterval), hipMemcpyHostToDevice, s));
-    if (items)
-        HIP_TRY(c, hipMemcpyAsync(c->b_item.p, h_item, items * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(c->b_hdr.p, h_hdr, sizeof(sv::BatchHeader), hipMemcpyHostToDevice, s));
-
-    c->ev_valid = false;
-    HIP_TRY(c, hipEventRecord(c->ev_start, s));
-    HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
-    HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-    c->ev_valid = true;
-    HIP_TRY(c, hipStreamSynchronize(s));
-    const unsigned long long *h_counts = static_cast<const unsigned long long *>(c->s_counts.p);
+    SV_HIP_TRY(c, hipEventSynchronize(c->batch.done));
+    c->batch.pending = false;
+    const unsigned long long *h_counts = sv::counts_host(c->batch);
     for (uint32_t i = 0; i < n; ++i)
         pi_out[i] = h_counts[i] + ((iv[i].lo <= 2 && 2 < iv[i].hi) ? 1 : 0);
     return SIEVE_OK;

@@ -1,0 +1,132 @@
+// Host runtime internals shared by the C ABI (sieve_api.hip) and the serving
+// loop (sieve_serve.hip).  Not part of the public ABI.
+#pragma once
+
+#include <vector>
+
+#include "sieve.h"
+#include "sieve_internal.h"
+
+namespace sv {
+
+constexpr uint64_t kMaxPrimeLimit = 31622777;      // > isqrt(SIEVE_MAX_HI)
+constexpr uint64_t kDefaultPrimeLimit = 1u << 20;  // covers hi <= 1.0995e12
+constexpr uint32_t kSegGranuleWords = 128;         // 4096 bits
+constexpr uint32_t kDefaultMaxSegWords = 16384;    // 2^19 bits = 64 KiB of LDS
+constexpr uint64_t kDefaultBudget = 32ull << 30;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct HostBuf {  // pinned host memory
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Everything a captured batch graph bakes in.
+struct GraphKey {
+    const void *iv, *item, *hdr, *counts, *h_counts, *primes, *inv;
+    uint32_t *words;
+    uint32_t seg_words, threads, blocks, max_intervals;
+    size_t counts_bytes;
+    bool operator==(const GraphKey &o) const
+    {
+        return iv == o.iv && item == o.item && hdr == o.hdr && counts == o.counts &&
+               h_counts == o.h_counts && primes == o.primes && inv == o.inv && words == o.words &&
+               seg_words == o.seg_words && threads == o.threads && blocks == o.blocks &&
+               max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
+    }
+};
+
+// One batch in flight: the interval table and work list (pinned staging and
+// device copies), per-interval counts, the batch header and the captured
+// graph that launches it.  A context owns one; the server owns one per lane.
+struct BatchEngine {
+    DevBuf iv, item, counts, hdr;
+    HostBuf s_iv, s_item, s_counts, s_hdr;
+    std::vector<uint32_t> order, nmark, ndense;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphKey key{};
+    hipEvent_t done = nullptr;  // recorded after the last launch
+    bool pending = false;       // a launch has been recorded on `done`
+    uint32_t n = 0;             // intervals staged
+    uint64_t items = 0;         // work items staged
+    uint32_t seg_words = 0, dense_limit = 0, threads = 0;
+};
+
+}  // namespace sv
+
+struct sieve_ctx {
+    int device = 0;
+    uint32_t n_cu = 0;
+    uint32_t lds_max = 0;  // LDS bytes one workgroup may use
+    uint32_t lds_per_cu = 0;
+    uint64_t hbm_budget = sv::kDefaultBudget;
+    hipStream_t stream = nullptr;
+    sieve_tuning tuning{};
+    int last_hip = 0;
+
+    // base primes: all odd primes <= primes_limit, ascending
+    uint64_t primes_limit = 0;
+    std::vector<uint32_t> h_primes;
+    uint32_t *d_primes = nullptr;
+    double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
+
+    // Per-call device words {count, segment queue}: kSlots slots used in
+    // turn, each guarded by an event so that an asynchronous call still
+    // running on another stream never sees its slot reset.
+    static constexpr int kSlots = 16;
+    unsigned long long *d_count = nullptr;  // 2 * kSlots words
+    hipEvent_t slot_done[kSlots] = {};
+    bool slot_used[kSlots] = {};
+    int next_slot = 0;
+    unsigned long long *h_count = nullptr;  // pinned
+
+    // events bracketing the last sieve kernel launch (range or batch)
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    bool ev_valid = false;
+
+    sv::BatchEngine batch;
+};
+
+namespace sv {
+
+#define SV_HIP_TRY(ctx, expr)                       \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) {                     \
+            (ctx)->last_hip = static_cast<int>(e_); \
+            return SIEVE_EDEVICE;                   \
+        }                                           \
+    } while (0)
+
+uint64_t isqrt_u64(uint64_t n);
+int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
+              sieve_plan_info *out);
+int ensure_primes(sieve_ctx *c, uint64_t bound);
+void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32_t *n_mark,
+                    uint32_t *n_dense);
+// The plain path: sieve [lo, hi) into d_words (may be null) and/or count it.
+int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t *pi_out,
+              hipStream_t s);
+int grow(sieve_ctx *c, DevBuf &b, size_t bytes);
+int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes);
+
+// Batch engine.  stage: validate the intervals and build the work list in
+// the engine's pinned staging (waits for the engine's previous launch).
+// launch: upload and launch the batch graph on s (asynchronous); the counts
+// (excluding the even prime 2) land in counts_host() once `done` completes.
+int engine_init(sieve_ctx *c, BatchEngine &e);
+void engine_free(BatchEngine &e);
+int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
+                 uint64_t total_words);
+int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed);
+inline const unsigned long long *counts_host(const BatchEngine &e)
+{
+    return static_cast<const unsigned long long *>(e.s_counts.p);
+}
+
+}  // namespace sv

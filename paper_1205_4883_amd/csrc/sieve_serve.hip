@@ -1,0 +1,601 @@
+// Serving loop with continuous batching (declared in sieve.h).
+//
+// One dispatcher thread owns the server's context.  Submitted requests wait
+// in arrival order until their device bytes fit the HBM budget and their
+// returned bitmap fits the pinned host arena (admission).  Whenever a lane
+// (a stream with its own batch engine and device output buffer) is free, the
+// dispatcher packs the admitted requests into one batch, launches its graph,
+// queues the bitmap copies to the requests' host buffers, and records an
+// event; lanes finish independently, so batches overlap on the device while
+// new arrivals form the next batch.  The plain mode serves one request at a
+// time with the plain range launch, for comparison.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sieve_runtime.h"
+
+namespace {
+
+uint64_t now_ns()
+{
+    return static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                     std::chrono::steady_clock::now().time_since_epoch())
+                                     .count());
+}
+
+// Pinned host arena with power-of-two size classes (4 KiB .. 2^40 B); freed
+// blocks go back to their class list.  When the arena is carved out and the
+// class list is empty, a block of its own is pinned (and later reused like
+// any other), so an admitted request always gets a buffer.  Not thread-safe:
+// guarded by the server mutex.
+class HostArena {
+  public:
+    int init(size_t bytes)
+    {
+        if (hipHostMalloc(&base_, bytes, hipHostMallocDefault) != hipSuccess) {
+            base_ = nullptr;
+            return SIEVE_ENOMEM;
+        }
+        size_ = bytes;
+        return SIEVE_OK;
+    }
+    ~HostArena()
+    {
+        if (base_)
+            (void)hipHostFree(base_);
+        for (void *p : extra_)
+            (void)hipHostFree(p);
+    }
+    static int cls(size_t bytes)
+    {
+        int c = 12;
+        while ((size_t(1) << c) < bytes)
+            ++c;
+        return c;
+    }
+    static size_t class_bytes(size_t bytes) { return size_t(1) << cls(bytes); }
+    void *alloc(size_t bytes)
+    {
+        const int c = cls(bytes);
+        if (!free_[c].empty()) {
+            void *p = free_[c].back();
+            free_[c].pop_back();
+            return p;
+        }
+        const size_t b = size_t(1) << c;
+        if (used_ + b <= size_) {
+            void *p = static_cast<char *>(base_) + used_;
+            used_ += b;
+            return p;
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        extra_.push_back(p);
+        return p;
+    }
+    void free(void *p, size_t bytes) { free_[cls(bytes)].push_back(p); }
+    size_t size() const { return size_; }
+
+  private:
+    void *base_ = nullptr;
+    size_t size_ = 0, used_ = 0;
+    std::vector<void *> free_[41];
+    std::vector<void *> extra_;
+};
+
+struct Request {
+    uint64_t id = 0, lo = 0, hi = 0, n_words = 0;
+    uint32_t flags = 0;
+    uint64_t dev_bytes = 0, host_bytes = 0;
+    uint64_t t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+    uint64_t pi = 0;
+    int status = SIEVE_OK;
+    uint32_t *host = nullptr;  // arena block for the bitmap
+};
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    sv::BatchEngine eng;
+    uint32_t *d_words = nullptr;  // max_batch_words
+    hipEvent_t copied = nullptr;  // after the bitmap copies
+    std::vector<Request *> reqs;
+    std::vector<sieve_interval> iv;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct sieve_server {
+    sieve_server_config cfg{};
+    sieve_ctx *ctx = nullptr;
+    std::vector<Lane> lanes;
+    HostArena arena;
+
+    std::mutex m;
+    std::condition_variable cv_work;  // dispatcher: new submissions or stop
+    std::condition_variable cv_done;  // pollers: new results
+    std::deque<Request *> pending;    // submitted, not admitted
+    std::deque<Request *> admitted;   // admitted, waiting for a lane
+    std::deque<Request *> done;       // finished, not yet polled
+    std::unordered_map<uint64_t, Request *> held;  // polled bitmap results, until release
+    uint64_t next_id = 1;
+    uint64_t admitted_bytes = 0, admitted_host = 0;
+    bool stop = false;
+    int fatal = SIEVE_OK;
+    sieve_server_stats stats{};
+    std::thread worker;
+};
+
+namespace {
+
+constexpr uint32_t kDefaultLanes = 3;
+constexpr uint32_t kDefaultMaxBatch = 1024;
+constexpr uint64_t kDefaultBatchWords = 1ull << 26;
+constexpr uint64_t kDefaultArena = 2ull << 30;
+
+// Admit from the head of the pending queue while both budgets allow.
+void admit_locked(sieve_server *s)
+{
+    while (!s->pending.empty()) {
+        Request *r = s->pending.front();
+        if (s->admitted_bytes + r->dev_bytes > s->cfg.hbm_budget_bytes ||
+            s->admitted_host + r->host_bytes > s->arena.size()) {
+            ++s->stats.deferred;
+            return;
+        }
+        s->admitted_bytes += r->dev_bytes;
+        s->admitted_host += r->host_bytes;
+        s->stats.peak_admitted_bytes = std::max<uint64_t>(s->stats.peak_admitted_bytes, s->admitted_bytes);
+        r->t_admit = now_ns();
+        s->pending.pop_front();
+        s->admitted.push_back(r);
+    }
+}
+
+void finish_locked(sieve_server *s, Request *r)
+{
+    s->admitted_bytes -= r->dev_bytes;
+    s->admitted_host -= r->host_bytes;
+    r->t_done = now_ns();
+    ++s->stats.completed;
+    s->done.push_back(r);
+}
+
+// Take admitted requests for one batch (under the lock): host buffers are
+// carved here so that the copies have a destination.
+void take_batch_locked(sieve_server *s, Lane &lane)
+{
+    uint64_t words = 0;
+    lane.reqs.clear();
+    while (!s->admitted.empty() && lane.reqs.size() < s->cfg.max_batch) {
+        Request *r = s->admitted.front();
+        const uint64_t w = (r->flags & SIEVE_WANT_BITMAP) ? r->n_words : 0;
+        if (words + w > s->cfg.max_batch_words)
+            break;
+        if (w) {
+            r->host = static_cast<uint32_t *>(s->arena.alloc(r->host_bytes));
+            if (!r->host)
+                break;  // arena fragmented: wait for releases
+        }
+        words += w;
+        s->admitted.pop_front();
+        lane.reqs.push_back(r);
+    }
+}
+
+int launch_batch_lane(sieve_server *s, Lane &lane)
+{
+    sieve_ctx *c = s->ctx;
+    const uint32_t n = static_cast<uint32_t>(lane.reqs.size());
+    lane.iv.resize(n);
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const Request *r = lane.reqs[i];
+        sieve_interval &v = lane.iv[i];
+        v.lo = r->lo;
+        v.hi = r->hi;
+        v.flags = r->flags & SIEVE_WANT_BITMAP;
+        v.pad = 0;
+        v.word_offset = v.flags ? off : 0;
+        if (v.flags)
+            off += r->n_words;
+    }
+    if (int st = sv::engine_stage(c, lane.eng, lane.iv.data(), n, lane.d_words, s->cfg.max_batch_words))
+        return st;
+    const uint64_t t = now_ns();
+    for (Request *r : lane.reqs)
+        r->t_launch = t;
+    if (int st = sv::engine_launch(c, lane.eng, lane.d_words, lane.stream, false))
+        return st;
+    for (uint32_t i = 0; i < n; ++i) {
+        const Request *r = lane.reqs[i];
+        if ((r->flags & SIEVE_WANT_BITMAP) && r->n_words)
+            SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words + lane.iv[i].word_offset, r->n_words * 4,
+                                         hipMemcpyDeviceToHost, lane.stream));
+    }
+    SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
+    lane.busy = true;
+    return SIEVE_OK;
+}
+
+// Plain mode: one request, plain range launch, bitmap copy, wait.
+int serve_plain(sieve_server *s, Lane &lane, Request *r)
+{
+    sieve_ctx *c = s->ctx;
+    r->t_launch = now_ns();
+    uint64_t pi = 0;
+    const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
+    if (int st = sv::run_range(c, r->lo, r->hi, bm ? lane.d_words : nullptr, &pi, lane.stream))
+        return st;
+    if (bm) {
+        SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words, r->n_words * 4, hipMemcpyDeviceToHost,
+                                     lane.stream));
+        SV_HIP_TRY(c, hipStreamSynchronize(lane.stream));
+    }
+    r->pi = pi;
+    return SIEVE_OK;
+}
+
+void dispatcher(sieve_server *s)
+{
+    sieve_ctx *c = s->ctx;
+    (void)hipSetDevice(c->device);
+    const bool plain = s->cfg.mode == SIEVE_SERVE_PLAIN;
+    for (;;) {
+        bool progressed = false;
+        // 1. retire finished lanes
+        for (Lane &lane : s->lanes) {
+            if (!lane.busy || hipEventQuery(lane.copied) != hipSuccess)
+                continue;
+            lane.eng.pending = false;
+            const unsigned long long *cnt = sv::counts_host(lane.eng);
+            std::lock_guard<std::mutex> g(s->m);
+            for (size_t i = 0; i < lane.reqs.size(); ++i) {
+                Request *r = lane.reqs[i];
+                r->pi = cnt[i] + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
+                finish_locked(s, r);
+            }
+            lane.reqs.clear();
+            lane.busy = false;
+            progressed = true;
+            s->cv_done.notify_all();
+        }
+        // 2. admit and launch on free lanes
+        int inflight = 0;
+        for (Lane &lane : s->lanes)
+            inflight += lane.busy ? 1 : 0;
+        for (Lane &lane : s->lanes) {
+            if (lane.busy)
+                continue;
+            {
+                std::lock_guard<std::mutex> g(s->m);
+                admit_locked(s);
+                if (plain) {
+                    lane.reqs.clear();
+                    if (!s->admitted.empty()) {
+                        Request *r = s->admitted.front();
+                        const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
+                        if (bm)
+                            r->host = static_cast<uint32_t *>(s->arena.alloc(r->host_bytes));
+                        if (!bm || r->host) {
+                            s->admitted.pop_front();
+                            lane.reqs.push_back(r);
+                        }
+                    }
+                } else {
+                    take_batch_locked(s, lane);
+                }
+            }
+            if (lane.reqs.empty())
+                break;
+            int st;
+            if (plain) {
+                st = serve_plain(s, lane, lane.reqs[0]);
+                std::lock_guard<std::mutex> g(s->m);
+                ++s->stats.batches;
+                s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, 1);
+                s->stats.max_inflight = std::max<uint64_t>(s->stats.max_inflight, 1);
+                lane.reqs[0]->status = st;
+                finish_locked(s, lane.reqs[0]);
+                lane.reqs.clear();
+                s->cv_done.notify_all();
+            } else {
+                st = launch_batch_lane(s, lane);
+                std::lock_guard<std::mutex> g(s->m);
+                ++s->stats.batches;
+                s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, lane.reqs.size());
+                s->stats.max_inflight = std::max<uint64_t>(s->stats.max_inflight, ++inflight);
+                if (st != SIEVE_OK) {
+                    for (Request *r : lane.reqs) {
+                        r->status = st;
+                        finish_locked(s, r);
+                    }
+                    lane.reqs.clear();
+                    lane.busy = false;
+                    s->fatal = st;
+                    s->cv_done.notify_all();
+                }
+            }
+            progressed = true;
+        }
+        // 3. sleep when idle
+        std::unique_lock<std::mutex> lk(s->m);
+        bool busy = false;
+        for (Lane &lane : s->lanes)
+            busy = busy || lane.busy;
+        if (s->stop && !busy && s->pending.empty() && s->admitted.empty())
+            return;
+        if (!progressed) {
+            if (busy)  // a batch is running: poll its event again soon
+                s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else if (s->pending.empty() && s->admitted.empty() && !s->stop)
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            else
+                s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_server **out)
+{
+    if (!out)
+        return SIEVE_EINVAL;
+    sieve_server *s = new (std::nothrow) sieve_server();
+    if (!s)
+        return SIEVE_ENOMEM;
+    if (cfg)
+        s->cfg = *cfg;
+    if (s->cfg.mode > SIEVE_SERVE_PLAIN) {
+        delete s;
+        return SIEVE_EINVAL;
+    }
+    if (!s->cfg.lanes)
+        s->cfg.lanes = s->cfg.mode == SIEVE_SERVE_PLAIN ? 1 : kDefaultLanes;
+    if (!s->cfg.max_batch)
+        s->cfg.max_batch = kDefaultMaxBatch;
+    if (!s->cfg.max_batch_words)
+        s->cfg.max_batch_words = kDefaultBatchWords;
+    if (!s->cfg.hbm_budget_bytes)
+        s->cfg.hbm_budget_bytes = sv::kDefaultBudget;
+    if (!s->cfg.host_arena_bytes)
+        s->cfg.host_arena_bytes = kDefaultArena;
+    if (s->cfg.lanes > 16 || s->cfg.max_batch_words > (1ull << 32)) {
+        delete s;
+        return SIEVE_EINVAL;
+    }
+    int st = sieve_create(&s->ctx, hip_device, s->cfg.hbm_budget_bytes);
+    if (st == SIEVE_OK)
+        st = s->arena.init(s->cfg.host_arena_bytes);
+    s->lanes.resize(s->cfg.lanes);
+    for (Lane &lane : s->lanes) {
+        if (st != SIEVE_OK)
+            break;
+        hipError_t e = hipStreamCreateWithFlags(&lane.stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&lane.copied, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipMalloc(&lane.d_words, s->cfg.max_batch_words * 4);
+        if (e != hipSuccess)
+            st = e == hipErrorOutOfMemory ? SIEVE_ENOMEM : SIEVE_EDEVICE;
+        if (st == SIEVE_OK)
+            st = sv::engine_init(s->ctx, lane.eng);
+    }
+    if (st != SIEVE_OK) {
+        s->stop = true;
+        sieve_server_destroy(s);
+        return st;
+    }
+    s->worker = std::thread(dispatcher, s);
+    *out = s;
+    return SIEVE_OK;
+}
+
+int sieve_server_submit(sieve_server *s, uint64_t lo, uint64_t hi, uint32_t flags, uint64_t *id_out)
+{
+    if (!s || !id_out || lo > hi)
+        return SIEVE_EINVAL;
+    if (hi > SIEVE_MAX_HI)
+        return SIEVE_ERANGE;
+    Request *r = new (std::nothrow) Request();
+    if (!r)
+        return SIEVE_ENOMEM;
+    r->lo = lo;
+    r->hi = hi;
+    r->flags = flags & SIEVE_WANT_BITMAP;
+    r->n_words = sieve_bitmap_words(lo, hi);
+    const bool bm = r->flags && r->n_words;
+    r->dev_bytes = bm ? r->n_words * 4 : 0;
+    r->host_bytes = bm ? HostArena::class_bytes(r->n_words * 4) : 0;
+    if (r->n_words > s->cfg.max_batch_words && bm) {
+        delete r;
+        return SIEVE_ENOMEM;
+    }
+    if (r->dev_bytes > s->cfg.hbm_budget_bytes || r->host_bytes > s->arena.size()) {
+        delete r;
+        return SIEVE_ENOMEM;
+    }
+    r->t_submit = now_ns();
+    {
+        std::lock_guard<std::mutex> g(s->m);
+        if (s->stop) {
+            delete r;
+            return SIEVE_EINVAL;
+        }
+        r->id = s->next_id++;
+        *id_out = r->id;
+        ++s->stats.submitted;
+        s->pending.push_back(r);
+    }
+    s->cv_work.notify_one();
+    return SIEVE_OK;
+}
+
+int sieve_server_poll(sieve_server *s, sieve_result *out, uint32_t max, uint32_t *n_out, uint32_t wait_us)
+{
+    if (!s || !n_out || (max && !out))
+        return SIEVE_EINVAL;
+    std::unique_lock<std::mutex> lk(s->m);
+    if (s->done.empty() && wait_us)
+        s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [&] { return !s->done.empty(); });
+    uint32_t k = 0;
+    while (k < max && !s->done.empty()) {
+        Request *r = s->done.front();
+        s->done.pop_front();
+        sieve_result &o = out[k++];
+        o.id = r->id;
+        o.lo = r->lo;
+        o.hi = r->hi;
+        o.pi = r->pi;
+        o.words = r->host;
+        o.n_words = r->host ? r->n_words : 0;
+        o.t_submit_ns = r->t_submit;
+        o.t_admit_ns = r->t_admit;
+        o.t_launch_ns = r->t_launch;
+        o.t_done_ns = r->t_done;
+        o.status = r->status;
+        o.flags = r->flags;
+        if (r->host)
+            s->held[r->id] = r;
+        else
+            delete r;
+    }
+    *n_out = k;
+    return SIEVE_OK;
+}
+
+int sieve_server_release(sieve_server *s, uint64_t id)
+{
+    if (!s)
+        return SIEVE_EINVAL;
+    std::lock_guard<std::mutex> g(s->m);
+    auto it = s->held.find(id);
+    if (it == s->held.end())
+        return SIEVE_EINVAL;
+    Request *r = it->second;
+    s->arena.free(r->host, r->host_bytes);
+    s->held.erase(it);
+    delete r;
+    s->cv_work.notify_one();  // freed host memory may let a batch form
+    return SIEVE_OK;
+}
+
+int sieve_server_get_stats(sieve_server *s, sieve_server_stats *out)
+{
+    if (!s || !out)
+        return SIEVE_EINVAL;
+    std::lock_guard<std::mutex> g(s->m);
+    *out = s->stats;
+    return s->fatal;
+}
+
+int sieve_server_destroy(sieve_server *s)
+{
+    if (!s)
+        return SIEVE_OK;
+    {
+        std::lock_guard<std::mutex> g(s->m);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable())
+        s->worker.join();
+    for (Lane &lane : s->lanes) {
+        if (s->ctx)
+            sv::engine_free(lane.eng);
+        if (lane.d_words)
+            (void)hipFree(lane.d_words);
+        if (lane.copied)
+            (void)hipEventDestroy(lane.copied);
+        if (lane.stream)
+            (void)hipStreamDestroy(lane.stream);
+    }
+    for (Request *r : s->done)
+        delete r;
+    for (auto &kv : s->held)
+        delete kv.second;
+    for (Request *r : s->pending)
+        delete r;
+    for (Request *r : s->admitted)
+        delete r;
+    if (s->ctx)
+        sieve_destroy(s->ctx);
+    delete s;
+    return SIEVE_OK;
+}
+
+int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint64_t *lo, const uint64_t *hi,
+                      const uint32_t *flags, const double *t_arrival_s, uint64_t n, uint64_t *pi_out,
+                      double *latency_ms_out, sieve_server_stats *stats_out)
+{
+    if (!lo || !hi || !flags || !t_arrival_s || !pi_out || !latency_ms_out)
+        return SIEVE_EINVAL;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (lo[i] > hi[i])
+            return SIEVE_EINVAL;
+        if (hi[i] > SIEVE_MAX_HI)
+            return SIEVE_ERANGE;
+    }
+    sieve_server *s = nullptr;
+    if (int st = sieve_server_create(hip_device, cfg, &s))
+        return st;
+    int sub_status = SIEVE_OK;
+    std::thread submitter([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (uint64_t i = 0; i < n; ++i) {
+            const auto due = t0 + std::chrono::nanoseconds(static_cast<int64_t>(t_arrival_s[i] * 1e9));
+            // sleep most of the way, then spin for the last stretch
+            const auto early = due - std::chrono::microseconds(200);
+            if (std::chrono::steady_clock::now() < early)
+                std::this_thread::sleep_until(early);
+            while (std::chrono::steady_clock::now() < due) {
+            }
+            uint64_t id = 0;  // ids are 1, 2, ... in submission order
+            const int st = sieve_server_submit(s, lo[i], hi[i], flags[i], &id);
+            if (st != SIEVE_OK) {
+                sub_status = st;
+                return;
+            }
+        }
+    });
+    uint64_t got = 0;
+    int status = SIEVE_OK;
+    std::vector<sieve_result> buf(256);
+    while (got < n) {
+        uint32_t k = 0;
+        sieve_server_poll(s, buf.data(), static_cast<uint32_t>(buf.size()), &k, 1000);
+        for (uint32_t j = 0; j < k; ++j) {
+            const sieve_result &r = buf[j];
+            const uint64_t i = r.id - 1;
+            if (r.status != SIEVE_OK)
+                status = r.status;
+            if (i < n) {
+                pi_out[i] = r.pi;
+                latency_ms_out[i] = (r.t_done_ns - r.t_submit_ns) * 1e-6;
+            }
+            if (r.words)
+                sieve_server_release(s, r.id);
+        }
+        got += k;
+        if (sub_status != SIEVE_OK)
+            break;
+    }
+    submitter.join();
+    if (stats_out)
+        sieve_server_get_stats(s, stats_out);
+    sieve_server_destroy(s);
+    return sub_status != SIEVE_OK ? sub_status : status;
+}
+
+}  // extern "C"

@@ -29,7 +29,12 @@ EXPORTED = [
     "sieve_last_kernel_ms",
     "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
     "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
+    "sieve_server_create", "sieve_server_submit", "sieve_server_poll", "sieve_server_release",
+    "sieve_server_get_stats", "sieve_server_destroy", "sieve_serve_trace",
 ]
+
+SIEVE_SERVE_BATCHED = 0
+SIEVE_SERVE_PLAIN = 1
 
 
 class sieve_tuning(ctypes.Structure):
@@ -49,6 +54,28 @@ class sieve_interval(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64),
                 ("word_offset", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32)]
+
+
+class sieve_server_config(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("max_batch_words", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("host_arena_bytes", ctypes.c_uint64), ("mode", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+class sieve_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64),
+                ("pi", ctypes.c_uint64), ("words", ctypes.c_void_p), ("n_words", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class sieve_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("max_batch_seen", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("peak_admitted_bytes", ctypes.c_uint64)]
 
 
 INTERVAL_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8"), ("word_offset", "<u8"),
@@ -91,6 +118,14 @@ def _lib():
     lib.sieve_range_count.argtypes = [vp, u64, u64, u64p, vp]
     lib.sieve_range_bitmap.argtypes = [vp, u64, u64, vp, u64, u64p, vp]
     lib.sieve_batch.argtypes = [vp, vp, u32, vp, u64, vp, vp]
+    lib.sieve_server_create.argtypes = [i32, ctypes.POINTER(sieve_server_config), ctypes.POINTER(vp)]
+    lib.sieve_server_submit.argtypes = [vp, u64, u64, u32, u64p]
+    lib.sieve_server_poll.argtypes = [vp, ctypes.POINTER(sieve_result), u32, ctypes.POINTER(u32), u32]
+    lib.sieve_server_release.argtypes = [vp, u64]
+    lib.sieve_server_get_stats.argtypes = [vp, ctypes.POINTER(sieve_server_stats)]
+    lib.sieve_server_destroy.argtypes = [vp]
+    lib.sieve_serve_trace.argtypes = [i32, ctypes.POINTER(sieve_server_config), vp, vp, vp, vp, u64,
+                                      vp, vp, ctypes.POINTER(sieve_server_stats)]
     for name in EXPORTED:
         if name not in ("sieve_strerror", "sieve_bitmap_words"):
             getattr(lib, name).restype = i32
@@ -192,6 +227,112 @@ def sieve_batch(ctx, intervals, d_words=None, total_words=0, stream=None):
     _check(_lib().sieve_batch(ctx, iv.ctypes.data, len(iv), ctypes.c_void_p(ptr), total_words,
                               pi.ctypes.data, _stream_ptr(stream)), "sieve_batch")
     return pi[: len(iv)]
+
+
+def _server_config(cfg):
+    c = sieve_server_config()
+    for k, v in (cfg or {}).items():
+        setattr(c, k, v)
+    return c
+
+
+def sieve_server_create(hip_device=0, **cfg):
+    srv = ctypes.c_void_p()
+    c = _server_config(cfg)
+    _check(_lib().sieve_server_create(hip_device, ctypes.byref(c), ctypes.byref(srv)),
+           "sieve_server_create")
+    return srv
+
+
+def sieve_server_submit(srv, lo, hi, flags=0):
+    rid = ctypes.c_uint64(0)
+    _check(_lib().sieve_server_submit(srv, lo, hi, flags, ctypes.byref(rid)), "sieve_server_submit")
+    return rid.value
+
+
+def sieve_server_poll(srv, max_results=256, wait_us=0):
+    """Finished results as dicts; 'words' is the host address of a bitmap
+    result (release it with sieve_server_release) or 0."""
+    buf = (sieve_result * max(1, max_results))()
+    n = ctypes.c_uint32(0)
+    _check(_lib().sieve_server_poll(srv, buf, max_results, ctypes.byref(n), wait_us),
+           "sieve_server_poll")
+    return [{k: getattr(buf[i], k) or 0 for k, _ in sieve_result._fields_} for i in range(n.value)]
+
+
+def result_words(result):
+    """Copy of a bitmap result's words as a numpy uint32 array."""
+    if not result["words"]:
+        return np.zeros(0, dtype=np.uint32)
+    arr = (ctypes.c_uint32 * result["n_words"]).from_address(result["words"])
+    return np.frombuffer(arr, dtype=np.uint32).copy()
+
+
+def sieve_server_release(srv, rid):
+    _check(_lib().sieve_server_release(srv, rid), "sieve_server_release")
+
+
+def sieve_server_get_stats(srv):
+    st = sieve_server_stats()
+    _check(_lib().sieve_server_get_stats(srv, ctypes.byref(st)), "sieve_server_get_stats")
+    return {k: getattr(st, k) for k, _ in sieve_server_stats._fields_}
+
+
+def sieve_server_destroy(srv):
+    _check(_lib().sieve_server_destroy(srv), "sieve_server_destroy")
+
+
+def sieve_serve_trace(hip_device, lo, hi, flags, t_arrival_s, **cfg):
+    """Replay a timed trace natively; returns (pi, latency_ms, stats)."""
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    hi = np.ascontiguousarray(hi, dtype=np.uint64)
+    flags = np.ascontiguousarray(flags, dtype=np.uint32)
+    t = np.ascontiguousarray(t_arrival_s, dtype=np.float64)
+    n = lo.size
+    pi = np.zeros(max(1, n), dtype=np.uint64)
+    lat = np.zeros(max(1, n), dtype=np.float64)
+    st = sieve_server_stats()
+    c = _server_config(cfg)
+    _check(_lib().sieve_serve_trace(hip_device, ctypes.byref(c), lo.ctypes.data, hi.ctypes.data,
+                                    flags.ctypes.data, t.ctypes.data, n, pi.ctypes.data,
+                                    lat.ctypes.data, ctypes.byref(st)), "sieve_serve_trace")
+    return pi[:n], lat[:n], {k: getattr(st, k) for k, _ in sieve_server_stats._fields_}
+
+
+class Server:
+    """A serving loop on one GPU; results come back as numpy arrays."""
+
+    def __init__(self, device=0, **cfg):
+        self.srv = sieve_server_create(device, **cfg)
+
+    def submit(self, lo, hi, bitmap=False):
+        return sieve_server_submit(self.srv, lo, hi, SIEVE_WANT_BITMAP if bitmap else 0)
+
+    def results(self, wait_us=1000):
+        """Finished results: dicts with 'id', 'pi', 'words' (numpy or None), timings."""
+        out = []
+        for r in sieve_server_poll(self.srv, 256, wait_us):
+            words = None
+            if r["words"]:
+                words = result_words(r)
+                sieve_server_release(self.srv, r["id"])
+            r = dict(r, words=words)
+            out.append(r)
+        return out
+
+    def stats(self):
+        return sieve_server_get_stats(self.srv)
+
+    def close(self):
+        if self.srv is not None:
+            sieve_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # -- convenience wrapper over torch tensors -----------------------------------

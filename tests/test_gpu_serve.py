@@ -1,0 +1,139 @@
+"""GPU tests of the serving loop: every result in the mix equals the same
+request sieved alone (plain launch), and equals the oracle on a sample."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    import paper_1205_4883_amd as sv
+
+    assert torch.cuda.is_available()
+    return sv
+
+
+@pytest.fixture(scope="module")
+def alone(sv):
+    s = sv.Sieve(0)
+    yield s
+    s.close()
+
+
+def _requests(seed, n, max_len=1e7):
+    rng = np.random.default_rng(seed)
+    lo = np.floor(np.exp(rng.uniform(np.log(1e3), np.log(1e12), n))).astype(np.uint64)
+    ln = np.floor(np.exp(rng.uniform(np.log(1e3), np.log(max_len), n))).astype(np.uint64)
+    bm = rng.random(n) < 0.5
+    return lo, lo + ln, bm
+
+
+def _drain(server, n, timeout_s=60):
+    got = {}
+    t0 = time.time()
+    while len(got) < n:
+        for r in server.results(wait_us=2000):
+            got[r["id"]] = r
+        assert time.time() - t0 < timeout_s, f"only {len(got)} of {n} results"
+    return got
+
+
+def _check_against_alone(alone, lo, hi, bm, ids, got):
+    for i in range(len(lo)):
+        r = got[ids[i]]
+        assert r["status"] == 0
+        words, pi = alone.bitmap(int(lo[i]), int(hi[i]))
+        assert r["pi"] == pi, (i, int(lo[i]), int(hi[i]))
+        if bm[i]:
+            assert np.array_equal(r["words"], words.cpu().numpy().view(np.uint32)), i
+        else:
+            assert r["words"] is None
+
+
+def test_server_mix_equals_alone_and_oracle(sv, alone, oracle_mod):
+    lo, hi, bm = _requests(21, 300)
+    server = sv.Server(0, lanes=3)
+    try:
+        print("case server mix of 300", flush=True)
+        ids = [server.submit(int(a), int(b), bool(f)) for a, b, f in zip(lo, hi, bm)]
+        got = _drain(server, len(ids))
+        st = server.stats()
+        assert st["completed"] == 300 and st["batches"] >= 1
+    finally:
+        server.close()
+    _check_against_alone(alone, lo, hi, bm, ids, got)
+    for i in range(0, 300, 10):
+        assert got[ids[i]]["pi"] == oracle_mod.count(int(lo[i]), int(hi[i]))
+
+
+def test_server_budget_defers_and_stays_exact(sv, alone):
+    # bitmaps of 125 KB .. 1 MB against a 1 MiB budget: admission must wait
+    rng = np.random.default_rng(5)
+    lo = rng.integers(10**9, 10**11, 60).astype(np.uint64)
+    hi = lo + rng.integers(2 * 10**6, 16 * 10**6, 60).astype(np.uint64)
+    bm = np.ones(60, dtype=bool)
+    server = sv.Server(0, lanes=2, hbm_budget_bytes=1 << 20, host_arena_bytes=1 << 22)
+    try:
+        ids = [server.submit(int(a), int(b), True) for a, b in zip(lo, hi)]
+        got = _drain(server, len(ids))
+        st = server.stats()
+        assert st["deferred"] > 0
+        assert st["peak_admitted_bytes"] <= 1 << 20
+    finally:
+        server.close()
+    _check_against_alone(alone, lo, hi, bm, ids, got)
+
+
+def test_server_plain_mode_matches(sv, alone):
+    lo, hi, bm = _requests(33, 60)
+    server = sv.Server(0, mode=sv.sieve.SIEVE_SERVE_PLAIN)
+    try:
+        ids = [server.submit(int(a), int(b), bool(f)) for a, b, f in zip(lo, hi, bm)]
+        got = _drain(server, len(ids))
+        assert server.stats()["max_batch_seen"] == 1
+    finally:
+        server.close()
+    _check_against_alone(alone, lo, hi, bm, ids, got)
+
+
+def test_server_argument_errors(sv):
+    server = sv.Server(0, max_batch_words=1024)
+    try:
+        with pytest.raises(sv.SieveError) as e:
+            server.submit(10, 5)
+        assert e.value.status == sv.sieve.SIEVE_EINVAL
+        with pytest.raises(sv.SieveError) as e:
+            server.submit(0, 10**15 + 1)
+        assert e.value.status == sv.sieve.SIEVE_ERANGE
+        with pytest.raises(sv.SieveError) as e:
+            server.submit(0, 10**6, bitmap=True)  # 15625 words > 1024 per batch
+        assert e.value.status == sv.sieve.SIEVE_ENOMEM
+        rid = server.submit(0, 10**6, bitmap=False)  # count only: no words needed
+        got = _drain(server, 1)
+        assert got[rid]["pi"] == 78498
+        with pytest.raises(sv.SieveError):
+            sv.sieve_server_release(server.srv, 987654321)
+    finally:
+        server.close()
+
+
+def test_serve_trace_batched_equals_plain_and_oracle(sv, oracle_mod):
+    from paper_1205_4883_amd import workloads
+
+    tr = workloads.serve_trace(1, seconds=1.0)
+    n = tr["t"].size
+    flags = tr["bitmap"].astype(np.uint32)
+    print(f"case serve trace 1 s ({n} requests)", flush=True)
+    pi_b, lat_b, st_b = sv.sieve_serve_trace(0, tr["lo"], tr["hi"], flags, tr["t"])
+    pi_p, lat_p, st_p = sv.sieve_serve_trace(0, tr["lo"], tr["hi"], flags, tr["t"],
+                                             mode=sv.sieve.SIEVE_SERVE_PLAIN)
+    assert st_b["completed"] == n and st_p["completed"] == n
+    assert np.array_equal(pi_b, pi_p)
+    assert np.all(lat_b > 0) and np.all(lat_p > 0)
+    for i in range(0, n, 100):
+        assert int(pi_b[i]) == oracle_mod.count(int(tr["lo"][i]), int(tr["hi"][i])), i
