@@ -133,18 +133,18 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
     return rec
 
 
-def run_serve(sv, seconds, modes=("batched", "plain")):
-    """Replay the served workload (Poisson arrivals at 2000 req/s, seed 1) for
-    `seconds` through the native server in each mode; latency is arrival to
-    result on the host."""
+def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
+    """Replay the served workload (Poisson arrivals, seed 1) for `seconds`
+    through the native server in each mode; latency is arrival to result on
+    the host."""
     import numpy as np
 
     from paper_1205_4883_amd import workloads
 
-    tr = workloads.serve_trace(1, seconds=seconds)
+    tr = workloads.serve_trace(1, seconds=seconds, rate=rate)
     flags = tr["bitmap"].astype(np.uint32)
     ints = int((tr["hi"] - tr["lo"]).sum())
-    out = {"workload": f"served sieve: Poisson arrivals at 2000 req/s for {seconds:g} s (seed 1), "
+    out = {"workload": f"served sieve: Poisson arrivals at {rate:g} req/s for {seconds:g} s (seed 1), "
                        "lo log-uniform in [1e3, 1e12], length log-uniform in [1e3, 1e9], "
                        "50% bitmap-return; 32 GiB HBM budget",
            "requests": int(tr["t"].size), "integers": ints,
@@ -155,6 +155,7 @@ def run_serve(sv, seconds, modes=("batched", "plain")):
         pi, lat, st = sv.sieve_serve_trace(0, tr["lo"], tr["hi"], flags, tr["t"], mode=m)
         span = float(np.max(tr["t"] + lat * 1e-3))
         out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "span_s": span,
                      "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
                      "ints_per_s": ints / span, "batches": st["batches"],
                      "max_batch": st["max_batch_seen"], "max_inflight": st["max_inflight"]}
@@ -187,6 +188,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="trace length for the served workload (c5: 60, default line: 5)")
+    ap.add_argument("--serve-rates", default="20000,100000",
+                    help="c5 only: extra arrival rates (req/s) replayed for 2 s each, both modes")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain comparison in the default line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -220,6 +223,7 @@ def main():
     if args.workload == "c5":
         secs = args.serve_seconds or 60.0
         r = run_serve(sv, secs)
+        r["load_sweep"] = [run_serve(sv, 2.0, rate=float(x)) for x in args.serve_rates.split(",") if x]
         print(json.dumps({
             "metric": METRIC, "value": r["batched"]["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": 1e3 * secs, "higher_is_better": True,

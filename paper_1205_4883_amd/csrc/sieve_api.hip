@@ -383,9 +383,7 @@ int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
     drop_graph(eng);
     hipStream_t cs = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = sv::launch_batch(static_cast<const sv::BatchInterval *>(k.iv),
-                                    static_cast<const uint32_t *>(k.item),
-                                    static_cast<sv::BatchHeader *>(const_cast<void *>(k.hdr)),
+    hipError_t e = sv::launch_batch(static_cast<sv::BatchHeader *>(const_cast<void *>(k.blob)),
                                     k.max_intervals, static_cast<const uint32_t *>(k.primes),
                                     static_cast<const double *>(k.inv), k.words,
                                     static_cast<unsigned long long *>(const_cast<void *>(k.counts)),
@@ -419,15 +417,40 @@ int engine_init(sieve_ctx *c, BatchEngine &e)
     return SIEVE_OK;
 }
 
+namespace {
+// Byte layout of a staged blob for n intervals and `items` work items.
+uint64_t blob_items_offset(uint32_t n)
+{
+    const uint64_t iv_bytes = static_cast<uint64_t>(n) * sizeof(sv::BatchInterval);
+    return kBlobAlign + (iv_bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
+}
+uint64_t blob_bytes(uint32_t n, uint64_t items)
+{
+    return blob_items_offset(n) + std::max<uint64_t>(1, items) * sizeof(uint32_t);
+}
+}  // namespace
+
+int engine_reserve(sieve_ctx *c, BatchEngine &e, uint32_t n, uint64_t items)
+{
+    const uint64_t bytes = blob_bytes(n, items);
+    if (int st = grow_host(c, e.s_blob, bytes))
+        return st;
+    if (int st = grow(c, e.blob, bytes))
+        return st;
+    if (int st = grow(c, e.counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long)))
+        return st;
+    return grow_host(c, e.s_counts, e.counts.bytes);
+}
+
 void engine_free(BatchEngine &e)
 {
     if (e.done && e.pending)
         (void)hipEventSynchronize(e.done);
     drop_graph(e);
-    for (DevBuf *b : {&e.iv, &e.item, &e.counts, &e.hdr})
+    for (DevBuf *b : {&e.blob, &e.counts})
         if (b->p)
             (void)hipFree(b->p);
-    for (HostBuf *b : {&e.s_iv, &e.s_item, &e.s_counts, &e.s_hdr})
+    for (HostBuf *b : {&e.s_blob, &e.s_counts})
         if (b->p)
             (void)hipHostFree(b->p);
     if (e.done)
@@ -483,17 +506,15 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     if (e.pending)
         HIP_TRY(c, hipEventSynchronize(e.done));
     e.pending = false;
-    if (int st = grow_host(c, e.s_iv, std::max<uint64_t>(1, n) * sizeof(sv::BatchInterval)))
+    const uint64_t bytes = blob_bytes(n, items);
+    if (int st = grow_host(c, e.s_blob, bytes))
         return st;
-    if (int st = grow_host(c, e.s_item, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
-        return st;
-    if (int st = grow_host(c, e.s_hdr, sizeof(sv::BatchHeader)))
-        return st;
+    char *blob = static_cast<char *>(e.s_blob.p);
 
     // Intervals whose segments carry the most base primes go first, so the
     // cheapest work items are the ones left at the end of the queue.
-    sv::BatchInterval *h_iv = static_cast<sv::BatchInterval *>(e.s_iv.p);
-    uint32_t *h_item = static_cast<uint32_t *>(e.s_item.p);
+    sv::BatchInterval *h_iv = reinterpret_cast<sv::BatchInterval *>(blob + kBlobAlign);
+    uint32_t *h_item = reinterpret_cast<uint32_t *>(blob + blob_items_offset(n));
     e.order.resize(n);
     e.nmark.resize(n);
     e.ndense.resize(n);
@@ -523,11 +544,14 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
             h_item[next + k] = i;
         next += segs;
     }
-    sv::BatchHeader *h_hdr = static_cast<sv::BatchHeader *>(e.s_hdr.p);
+    sv::BatchHeader *h_hdr = reinterpret_cast<sv::BatchHeader *>(blob);
     h_hdr->n_intervals = n;
     h_hdr->n_items = static_cast<uint32_t>(items);
     h_hdr->queue = 0;
     h_hdr->pad = 0;
+    h_hdr->iv_off = kBlobAlign;
+    h_hdr->item_off = blob_items_offset(n);
+    e.blob_used = bytes;
     e.n = n;
     e.items = items;
     e.seg_words = sw;
@@ -539,23 +563,13 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
 int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed)
 {
     const uint32_t n = e.n;
-    if (int st = grow(c, e.iv, std::max<uint64_t>(1, n) * sizeof(sv::BatchInterval)))
-        return st;
-    if (int st = grow(c, e.item, std::max<uint64_t>(1, e.items) * sizeof(uint32_t)))
-        return st;
-    if (int st = grow(c, e.counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long)))
-        return st;
-    if (int st = grow(c, e.hdr, sizeof(sv::BatchHeader)))
-        return st;
-    if (int st = grow_host(c, e.s_counts, e.counts.bytes))
+    if (int st = engine_reserve(c, e, n, e.items))
         return st;
     uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(e.seg_words, e.threads));
     if (c->tuning.wg_per_cu)
         per_cu = std::min(per_cu, c->tuning.wg_per_cu);
     GraphKey k{};
-    k.iv = e.iv.p;
-    k.item = e.item.p;
-    k.hdr = e.hdr.p;
+    k.blob = e.blob.p;
     k.counts = e.counts.p;
     k.h_counts = e.s_counts.p;
     k.primes = c->d_primes + sv::kPresievePrimes;
@@ -569,10 +583,7 @@ int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s
     if (!e.exec || !(e.key == k))
         if (int st = capture_batch_graph(c, e, k))
             return st;
-    HIP_TRY(c, hipMemcpyAsync(e.iv.p, e.s_iv.p, n * sizeof(sv::BatchInterval), hipMemcpyHostToDevice, s));
-    if (e.items)
-        HIP_TRY(c, hipMemcpyAsync(e.item.p, e.s_item.p, e.items * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(e.hdr.p, e.s_hdr.p, sizeof(sv::BatchHeader), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(e.blob.p, e.s_blob.p, e.blob_used, hipMemcpyHostToDevice, s));
     if (timed) {
         c->ev_valid = false;
         HIP_TRY(c, hipEventRecord(c->ev_start, s));

@@ -49,13 +49,18 @@ struct BatchInterval {
     uint32_t pad;
 };
 
-// Sizes and work counter of a batch launch, in device memory.
+// Sizes and work counter of a batch launch, in device memory.  The header
+// starts one upload blob: the interval table sits at byte iv_off and the work
+// list (interval index of each item) at item_off, so one copy moves a batch.
 struct BatchHeader {
     uint32_t n_intervals;
     uint32_t n_items;
     uint32_t queue;  // next item; zeroed by the reset kernel
     uint32_t pad;
+    uint64_t iv_off;
+    uint64_t item_off;
 };
+constexpr uint64_t kBlobAlign = 256;
 
 // Launchers (sieve_kernels.hip).  All return the first HIP error.
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
@@ -75,12 +80,11 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
 
 // Reset kernel (counts[0 .. n_intervals) and the queue) followed by the
-// persistent batch kernel; both read their sizes from d_hdr.  max_intervals
-// sizes the reset grid.
-hipError_t launch_batch(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
-                        uint32_t max_intervals, const uint32_t *d_primes, const double *d_inv,
-                        uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
-                        uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
+// persistent batch kernel; both read their sizes and the table offsets from
+// the blob's header.  max_intervals sizes the reset grid.
+hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
+                        const double *d_inv, uint32_t *d_words, unsigned long long *d_counts,
+                        uint32_t seg_words, uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
 
 // The segment kernels are built for a few static LDS sizes: the smallest
 // capacity (in words) that holds seg_words (0 if none), the LDS bytes a

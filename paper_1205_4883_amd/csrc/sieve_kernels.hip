@@ -372,8 +372,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 // graph serves batches of any size up to its buffers' capacity.
 template <uint32_t kSegMax>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(
-    const BatchInterval *ivs, const uint32_t *item_iv, BatchHeader *hdr, const uint32_t *primes,
-    const double *inv, uint32_t *words, unsigned long long *counts, uint32_t seg_words)
+    BatchHeader *hdr, const uint32_t *primes, const double *inv, uint32_t *words,
+    unsigned long long *counts, uint32_t seg_words)
 {
     __shared__ uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
@@ -381,6 +381,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
     const uint32_t n_items = hdr->n_items;
+    const char *blob = reinterpret_cast<const char *>(hdr);
+    const BatchInterval *ivs = reinterpret_cast<const BatchInterval *>(blob + hdr->iv_off);
+    const uint32_t *item_iv = reinterpret_cast<const uint32_t *>(blob + hdr->item_off);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -616,13 +619,12 @@ void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words
 }
 
 template <uint32_t kSegMax>
-void launch_batch_cap(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
-                      const uint32_t *d_primes, const double *d_inv, uint32_t *d_words,
-                      unsigned long long *d_counts, uint32_t seg_words, uint32_t threads, uint32_t grid,
-                      hipStream_t s)
+void launch_batch_cap(BatchHeader *d_blob, const uint32_t *d_primes, const double *d_inv,
+                      uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
+                      uint32_t threads, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_iv, d_item_iv, d_hdr,
-                       d_primes, d_inv, d_words, d_counts, seg_words);
+    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_blob, d_primes, d_inv,
+                       d_words, d_counts, seg_words);
 }
 }  // namespace
 
@@ -697,22 +699,21 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchInterval *d_iv, const uint32_t *d_item_iv, BatchHeader *d_hdr,
-                        uint32_t max_intervals, const uint32_t *d_primes, const double *d_inv,
-                        uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
-                        uint32_t block_threads, uint32_t n_blocks, hipStream_t s)
+hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
+                        const double *d_inv, uint32_t *d_words, unsigned long long *d_counts,
+                        uint32_t seg_words, uint32_t block_threads, uint32_t n_blocks, hipStream_t s)
 {
     if (n_blocks == 0)
         return hipSuccess;
     const uint32_t reset_blocks = (max_intervals + 255) / 256 > 0 ? (max_intervals + 255) / 256 : 1;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(reset_blocks < 1024 ? reset_blocks : 1024), dim3(256), 0, s,
-                       d_hdr, d_counts);
+                       d_blob, d_counts);
     switch (seg_capacity_for(seg_words)) {
-    case 512: launch_batch_cap<512>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 2048: launch_batch_cap<2048>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 8192: launch_batch_cap<8192>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 16384: launch_batch_cap<16384>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 32768: launch_batch_cap<32768>(d_iv, d_item_iv, d_hdr, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

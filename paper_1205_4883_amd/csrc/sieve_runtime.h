@@ -27,16 +27,15 @@ struct HostBuf {  // pinned host memory
 
 // Everything a captured batch graph bakes in.
 struct GraphKey {
-    const void *iv, *item, *hdr, *counts, *h_counts, *primes, *inv;
+    const void *blob, *counts, *h_counts, *primes, *inv;
     uint32_t *words;
     uint32_t seg_words, threads, blocks, max_intervals;
     size_t counts_bytes;
     bool operator==(const GraphKey &o) const
     {
-        return iv == o.iv && item == o.item && hdr == o.hdr && counts == o.counts &&
-               h_counts == o.h_counts && primes == o.primes && inv == o.inv && words == o.words &&
-               seg_words == o.seg_words && threads == o.threads && blocks == o.blocks &&
-               max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
+        return blob == o.blob && counts == o.counts && h_counts == o.h_counts && primes == o.primes &&
+               inv == o.inv && words == o.words && seg_words == o.seg_words && threads == o.threads &&
+               blocks == o.blocks && max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
     }
 };
 
@@ -44,8 +43,9 @@ struct GraphKey {
 // device copies), per-interval counts, the batch header and the captured
 // graph that launches it.  A context owns one; the server owns one per lane.
 struct BatchEngine {
-    DevBuf iv, item, counts, hdr;
-    HostBuf s_iv, s_item, s_counts, s_hdr;
+    DevBuf blob, counts;  // blob: header, interval table, work list
+    HostBuf s_blob, s_counts;
+    uint64_t blob_used = 0;  // bytes of the staged blob
     std::vector<uint32_t> order, nmark, ndense;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -120,6 +120,9 @@ int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes);
 // launch: upload and launch the batch graph on s (asynchronous); the counts
 // (excluding the even prime 2) land in counts_host() once `done` completes.
 int engine_init(sieve_ctx *c, BatchEngine &e);
+// Grow the engine's buffers ahead of time for n intervals and `items` work
+// items, so that batches up to that size never re-capture the graph.
+int engine_reserve(sieve_ctx *c, BatchEngine &e, uint32_t n, uint64_t items);
 void engine_free(BatchEngine &e);
 int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                  uint64_t total_words);

@@ -391,6 +391,10 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
             st = e == hipErrorOutOfMemory ? SIEVE_ENOMEM : SIEVE_EDEVICE;
         if (st == SIEVE_OK)
             st = sv::engine_init(s->ctx, lane.eng);
+        // size the lane's batch buffers up front (a full batch of requests,
+        // each a few segments) so that batches rarely re-capture the graph
+        if (st == SIEVE_OK)
+            st = sv::engine_reserve(s->ctx, lane.eng, s->cfg.max_batch, 16ull * s->cfg.max_batch);
     }
     if (st != SIEVE_OK) {
         s->stop = true;
