@@ -166,6 +166,44 @@ def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
     return out
 
 
+def run_mr(sv, torch, steps, warmup, n=1 << 24):
+    """Batched deterministic Miller-Rabin on n random odd 64-bit integers
+    (seed 2), against the oracle's Miller-Rabin on the host."""
+    import numpy as np
+
+    import oracle  # CPU-baseline leg only
+
+    rng = np.random.default_rng(2)
+    ns = rng.integers(0, 2**63, n, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    s = sv.Sieve(0)
+    d_n = torch.from_numpy(ns.view(np.int64)).to("cuda:0")
+    out = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream(0)
+    for _ in range(warmup):
+        sv.sieve_is_prime_batch(s.ctx, d_n, n, out, stream=stream)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sv.sieve_is_prime_batch(s.ctx, d_n, n, out, stream=stream)
+        kms.append(sv.sieve_last_kernel_ms(s.ctx))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    got = out.cpu().numpy()
+    s.close()
+    sample = 1 << 16
+    t1 = time.perf_counter()
+    want = np.array([oracle.mr_is_prime(int(x)) for x in ns[:sample]], dtype=np.uint8)
+    cpu_dt = time.perf_counter() - t1
+    assert np.array_equal(got[:sample], want), "GPU and oracle Miller-Rabin differ"
+    return {"workload": f"deterministic Miller-Rabin of {n} random odd 64-bit integers (seed 2)",
+            "candidates": n, "primes": int(got.sum()), "ms_per_batch": 1e3 * dt,
+            "kernel_ms": float(np.mean(kms)), "candidates_per_s": n / dt,
+            "cpu_baseline": {"value": sample / cpu_dt, "unit": "candidates/s", "cores": 1,
+                             "kind": "oracle", "sample": f"first {sample} candidates, one thread, "
+                                                         "called one by one from Python"}}
+
+
 def cpu_baseline(lo, hi, expect_pi):
     import oracle  # CPU-baseline leg only
 
@@ -185,7 +223,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "mr"])
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="trace length for the served workload (c5: 60, default line: 5)")
     ap.add_argument("--serve-rates", default="20000,100000",
@@ -219,6 +257,16 @@ def main():
         return
 
     import paper_1205_4883_amd as sv
+
+    if args.workload == "mr":
+        r = run_mr(sv, torch, args.steps, args.warmup)
+        print(json.dumps({
+            "metric": "Miller-Rabin candidates/s (64-bit)", "value": r["candidates_per_s"],
+            "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": r["workload"]}, "mr": r}), flush=True)
+        return
 
     if args.workload == "c5":
         secs = args.serve_seconds or 60.0

@@ -26,8 +26,9 @@
  * Device buffers: pointers named d_* are device (HBM) addresses on the
  *   context's device, for example the data_ptr() of a torch tensor.  The
  *   caller owns them; the library never frees them.
- * Streams: a `stream` argument is a hipStream_t on the context's device, or
- *   NULL for the context's own stream.  Work is ordered on that stream.
+ * Streams: a `stream` argument is a hipStream_t on the context's device;
+ *   NULL is the device's default (null) stream, as in HIP.  Work is ordered on
+ *   that stream.
  * Threads: a context is used by one host thread at a time.
  */
 #ifndef SIEVE_H
@@ -189,6 +190,40 @@ typedef struct sieve_interval {
  * budget), SIEVE_EDEVICE. */
 SIEVE_API int sieve_batch(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                 uint64_t total_words, uint64_t *pi_out, void *stream);
+
+/* Batched primality of 64-bit integers (the paper's Section 3.2): out[i] = 1
+ * when n[i] is prime.  Deterministic Miller-Rabin (the test the paper points
+ * to), with the first k primes as bases for the published bounds below which
+ * they admit no strong pseudoprime, k <= 12 for every n < 2^64; the modular
+ * powers are Alg. 2's repeated squaring in Montgomery form.  d_n and d_out
+ * are DEVICE arrays of count entries (uint64, uint8).  Asynchronous on
+ * `stream`; sieve_last_kernel_ms times it.  Errors: SIEVE_EINVAL (NULL
+ * arrays), SIEVE_EDEVICE. */
+SIEVE_API int sieve_is_prime_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, uint8_t *d_out,
+                                   void *stream);
+
+/* The paper's Fermat test (Alg. 3) on a batch: out[i] = 1 when
+ * a^(n-1) = 1 (mod n) for every base a_j = d_draws[j] mod (n - 1) + 1,
+ * j < iterations (the caller supplies the random draws; DEVICE array).  n = 0
+ * and 1 fail, n = 2 passes.  Carmichael numbers pass for bases prime to them,
+ * as the paper warns.  Arguments and errors as for sieve_is_prime_batch. */
+SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, const uint64_t *d_draws,
+                                 uint32_t iterations, uint8_t *d_out, void *stream);
+
+/* Autotuner.  Times candidate tunings (segment size with a matching
+ * workgroup size, and the dense/sparse bound) on the given work - one
+ * interval is timed as sieve_range_count, several as a count-only
+ * sieve_batch - and returns the fastest in *best (and its kernel time in
+ * *best_ms if not NULL).  Results are cached per context by (single range
+ * or batch, decade of the largest hi, log2 of the total bitmap words); a
+ * cached answer is returned without timing unless SIEVE_TUNE_FORCE is set.
+ * With SIEVE_TUNE_APPLY the context keeps the winner; otherwise its tuning
+ * is left as it was.  The candidate search is the project's own (it is not
+ * in the paper).  Errors as for sieve_range_count / sieve_batch. */
+#define SIEVE_TUNE_APPLY 1u
+#define SIEVE_TUNE_FORCE 2u
+SIEVE_API int sieve_autotune(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, uint32_t flags,
+                             sieve_tuning *best, double *best_ms);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.

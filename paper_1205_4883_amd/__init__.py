@@ -19,9 +19,12 @@ from .sieve import (  # noqa: F401
     sieve_server_poll,
     sieve_server_release,
     sieve_server_submit,
+    sieve_autotune,
     sieve_base_primes,
     sieve_batch,
     sieve_bitmap_words,
+    sieve_fermat_batch,
+    sieve_is_prime_batch,
     sieve_create,
     sieve_destroy,
     sieve_get_tuning,

@@ -781,7 +781,7 @@ int sieve_range_count(sieve_ctx *c, uint64_t lo, uint64_t hi, uint64_t *pi_out, 
         return SIEVE_EINVAL;
     if (hi > SIEVE_MAX_HI)
         return SIEVE_ERANGE;
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
     return sv::run_range(c, lo, hi, nullptr, pi_out, s);
 }
 
@@ -799,7 +799,7 @@ int sieve_range_bitmap(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words
         return SIEVE_EINVAL;
     if (n_words < need)
         return SIEVE_EBUFSZ;
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
     return sv::run_range(c, lo, hi, d_words, pi_out, s);
 }
 
@@ -814,7 +814,7 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
         return SIEVE_OK;
     if (int st = sv::engine_stage(c, c->batch, iv, n, d_words, total_words))
         return st;
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
     if (int st = sv::engine_launch(c, c->batch, d_words, s, true))
         return st;
     SV_HIP_TRY(c, hipEventSynchronize(c->batch.done));
@@ -822,6 +822,94 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     const unsigned long long *h_counts = sv::counts_host(c->batch);
     for (uint32_t i = 0; i < n; ++i)
         pi_out[i] = h_counts[i] + ((iv[i].lo <= 2 && 2 < iv[i].hi) ? 1 : 0);
+    return SIEVE_OK;
+}
+
+int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t flags, sieve_tuning *best,
+                   double *best_ms)
+{
+    if (!c || !iv || n == 0 || !best)
+        return SIEVE_EINVAL;
+    uint64_t max_hi = 0, words = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (iv[i].lo > iv[i].hi)
+            return SIEVE_EINVAL;
+        if (iv[i].hi > SIEVE_MAX_HI)
+            return SIEVE_ERANGE;
+        max_hi = std::max(max_hi, iv[i].hi);
+        words += sieve_bitmap_words(iv[i].lo, iv[i].hi);
+    }
+    int decade = 0;
+    for (uint64_t x = max_hi; x >= 10; x /= 10)
+        ++decade;
+    int lg = 0;
+    for (uint64_t x = words; x > 1; x >>= 1)
+        ++lg;
+    const auto key = std::make_tuple(n > 1 ? 1 : 0, decade, lg);
+    auto hit = c->tune_cache.find(key);
+    if (hit != c->tune_cache.end() && !(flags & SIEVE_TUNE_FORCE)) {
+        *best = hit->second.first;
+        if (best_ms)
+            *best_ms = hit->second.second;
+        if (flags & SIEVE_TUNE_APPLY)
+            c->tuning = *best;
+        return SIEVE_OK;
+    }
+    // Segment sizes with the workgroup size that gives 16 waves per CU for
+    // that LDS footprint, times three dense/sparse bounds.
+    struct SegChoice {
+        uint32_t seg_bits, threads;
+    };
+    const SegChoice segs[] = {{1u << 17, 256}, {1u << 18, 256}, {1u << 19, 512}, {1u << 20, 1024}};
+    const uint32_t dense_div[] = {1024, 512, 256};
+    const sieve_tuning saved = c->tuning;
+    std::vector<sieve_interval> count_only(iv, iv + n);
+    for (auto &v : count_only)
+        v.flags = 0;
+    sieve_tuning win{};
+    double win_ms = 1e300;
+    int st = SIEVE_OK;
+    for (const SegChoice &sc : segs) {
+        if (sc.seg_bits / 32 > sv::max_seg_words(c->lds_max))
+            continue;
+        for (uint32_t dd : dense_div) {
+            sieve_tuning t = saved;
+            t.seg_bits = sc.seg_bits;
+            t.block_threads = sc.threads;
+            t.dense_limit = std::max(sc.seg_bits / dd, sv::kFirstMarkedPrime);
+            c->tuning = t;
+            double ms = 1e300;
+            for (int rep = 0; rep < 3 && st == SIEVE_OK; ++rep) {
+                if (n == 1) {
+                    uint64_t pi = 0;
+                    st = sv::run_range(c, iv[0].lo, iv[0].hi, nullptr, &pi, c->stream);
+                } else {
+                    std::vector<uint64_t> pi(n);
+                    st = sieve_batch(c, count_only.data(), n, nullptr, 0, pi.data(), nullptr);
+                }
+                double k = 0;
+                if (st == SIEVE_OK && rep > 0 && sieve_last_kernel_ms(c, &k) == SIEVE_OK)
+                    ms = std::min(ms, k);  // the first run is a warm-up
+            }
+            if (st != SIEVE_OK)
+                break;
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = t;
+            }
+        }
+        if (st != SIEVE_OK)
+            break;
+    }
+    c->tuning = saved;
+    if (st != SIEVE_OK)
+        return st;
+    c->tune_cache[key] = {win, win_ms};
+    *best = win;
+    if (best_ms)
+        *best_ms = win_ms;
+    if (flags & SIEVE_TUNE_APPLY)
+        c->tuning = win;
     return SIEVE_OK;
 }
 

@@ -1,0 +1,275 @@
+// Batched primality tests on the GPU: the paper's modular exponentiation by
+// repeated squaring (Section 3.2, Alg. 2) driving the Fermat test
+// (Alg. 3) and deterministic Miller-Rabin, the test the paper points to for
+// Carmichael numbers.  One lane per candidate n < 2^64; products modulo n
+// are Montgomery products with R = 2^64 (n odd), so no 128-bit division is
+// ever needed.
+#include "sieve_runtime.h"
+
+namespace sv {
+namespace {
+
+struct Mont {
+    uint64_t n;     // odd modulus
+    uint64_t ninv;  // -n^-1 mod 2^64
+    uint64_t one;   // R mod n
+};
+
+__device__ __forceinline__ uint64_t mul_hi(uint64_t a, uint64_t b)
+{
+    return __umul64hi(a, b);
+}
+
+// a * b * R^-1 mod n, for a, b < n.
+__device__ __forceinline__ uint64_t mont_mul(const Mont &m, uint64_t a, uint64_t b)
+{
+    const uint64_t t_lo = a * b;
+    const uint64_t t_hi = mul_hi(a, b);
+    const uint64_t q = t_lo * m.ninv;            // t + q*n = 0 mod R
+    const uint64_t qn_hi = mul_hi(q, m.n);
+    // (t + q*n) / R = t_hi + qn_hi + carry out of t_lo + q*n_lo (which is
+    // 0 mod R, so the carry is 1 exactly when t_lo != 0)
+    const uint64_t carry = t_lo != 0 ? 1 : 0;
+    uint64_t r = t_hi + qn_hi;
+    const bool ovf = r < t_hi;
+    const uint64_t r2 = r + carry;
+    const bool ovf2 = r2 < r;
+    r = r2;
+    if (ovf || ovf2 || r >= m.n)
+        r -= m.n;
+    return r;
+}
+
+__device__ __forceinline__ Mont mont_setup(uint64_t n)
+{
+    Mont m;
+    m.n = n;
+    uint64_t inv = n;  // n * n = 1 mod 8 for odd n: 3 correct bits
+    for (int i = 0; i < 5; ++i)
+        inv *= 2 - n * inv;  // Newton: doubles the correct low bits
+    m.ninv = 0 - inv;
+    m.one = (0 - n) % n;  // 2^64 mod n
+    return m;
+}
+
+// x R mod n for x < n: x doubled 64 times modulo n.
+__device__ __forceinline__ uint64_t to_mont(const Mont &m, uint64_t x)
+{
+    for (int i = 0; i < 64; ++i) {
+        const bool top = (x >> 63) != 0;
+        x <<= 1;
+        if (top || x >= m.n)
+            x -= m.n;
+    }
+    return x;
+}
+
+// base^e in Montgomery form by right-to-left repeated squaring (Alg. 2: x
+// collects the squares y = base^(2^k) for the set bits k of e).
+__device__ __forceinline__ uint64_t mont_pow(const Mont &m, uint64_t base_m, uint64_t e)
+{
+    uint64_t x = m.one;
+    uint64_t y = base_m;
+    while (e) {
+        if (e & 1)
+            x = mont_mul(m, x, y);
+        e >>= 1;
+        if (e)
+            y = mont_mul(m, y, y);
+    }
+    return x;
+}
+
+// One Miller-Rabin round: n - 1 = d * 2^s, d odd.  True when base a does not
+// prove n composite.
+__device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a, uint64_t d, int s)
+{
+    a %= m.n;
+    if (a == 0)
+        return true;
+    const uint64_t minus_one = m.n - m.one;  // (n - 1) R mod n
+    uint64_t x = mont_pow(m, to_mont(m, a), d);
+    if (x == m.one || x == minus_one)
+        return true;
+    for (int j = 1; j < s; ++j) {
+        x = mont_mul(m, x, x);
+        if (x == minus_one)
+            return true;
+    }
+    return false;
+}
+
+// Deterministic Miller-Rabin for n < 2^64 with the first k primes as bases,
+// k from the published bounds below which those bases admit no strong
+// pseudoprime (Jaeschke 1993; Sorenson and Webster 2015 for 12 bases).
+__device__ bool is_prime_u64(uint64_t n)
+{
+    constexpr uint32_t kBases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2)
+        return false;
+    for (int i = 0; i < 12; ++i) {
+        if (n == kBases[i])
+            return true;
+        if (n % kBases[i] == 0)
+            return false;
+    }
+    if (n < 41 * 41)  // no factor up to 37 and below 41^2: prime
+        return true;
+    int k;
+    if (n < 2047ull)
+        k = 1;
+    else if (n < 1373653ull)
+        k = 2;
+    else if (n < 25326001ull)
+        k = 3;
+    else if (n < 3215031751ull)
+        k = 4;
+    else if (n < 2152302898747ull)
+        k = 5;
+    else if (n < 3474749660383ull)
+        k = 6;
+    else if (n < 341550071728321ull)
+        k = 7;
+    else if (n < 3825123056546413051ull)
+        k = 9;
+    else
+        k = 12;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    const Mont m = mont_setup(n);
+    for (int i = 0; i < k; ++i)
+        if (!mr_round(m, kBases[i], d, s))
+            return false;
+    return true;
+}
+
+__global__ void __launch_bounds__(256) mr_kernel(const uint64_t *ns, uint64_t count, uint8_t *out)
+{
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x)
+        out[i] = is_prime_u64(ns[i]) ? 1 : 0;
+}
+
+// x + y mod n for x, y < n (the sum may pass 2^64).
+__device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t n)
+{
+    const uint64_t s = x + y;
+    return (s < x || s >= n) ? s - n : s;
+}
+
+// a * b mod n for any n > 1 by doubling and adding (64 steps).
+__device__ uint64_t mul_mod_slow(uint64_t a, uint64_t b, uint64_t n)
+{
+    uint64_t r = 0;
+    a %= n;
+    while (b) {
+        if (b & 1)
+            r = add_mod(r, a, n);
+        a = add_mod(a, a, n);
+        b >>= 1;
+    }
+    return r;
+}
+
+// Alg. 3: n passes when a^(n-1) = 1 mod n for every base a_j =
+// draws[j] mod (n - 1) + 1; n = 1 (and 0) fail, n = 2 passes.
+__global__ void __launch_bounds__(256) fermat_kernel(const uint64_t *ns, uint64_t count, const uint64_t *draws,
+                                                     uint32_t iterations, uint8_t *out)
+{
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t n = ns[i];
+        uint8_t pass = 1;
+        if (n <= 1) {
+            pass = 0;
+        } else if (n == 2) {
+            pass = 1;
+        } else if ((n & 1) == 0) {
+            // even n > 2 has no Montgomery form: shift-and-add products
+            for (uint32_t j = 0; j < iterations && pass; ++j) {
+                const uint64_t a = draws[j] % (n - 1) + 1;
+                uint64_t x = 1, y = a, e = n - 1;
+                while (e) {
+                    if (e & 1)
+                        x = mul_mod_slow(x, y, n);
+                    y = mul_mod_slow(y, y, n);
+                    e >>= 1;
+                }
+                pass = x == 1 ? 1 : 0;
+            }
+        } else {
+            const Mont m = mont_setup(n);
+            for (uint32_t j = 0; j < iterations && pass; ++j) {
+                const uint64_t a = draws[j] % (n - 1) + 1;
+                pass = mont_pow(m, to_mont(m, a), n - 1) == m.one ? 1 : 0;
+            }
+        }
+        out[i] = pass;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_is_prime(const uint64_t *d_n, uint64_t count, uint8_t *d_out, uint32_t blocks, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(mr_kernel, dim3(blocks), dim3(256), 0, s, d_n, count, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fermat(const uint64_t *d_n, uint64_t count, const uint64_t *d_draws, uint32_t iterations,
+                         uint8_t *d_out, uint32_t blocks, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fermat_kernel, dim3(blocks), dim3(256), 0, s, d_n, count, d_draws, iterations, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace sv
+
+extern "C" {
+
+int sieve_is_prime_batch(sieve_ctx *c, const uint64_t *d_n, uint64_t count, uint8_t *d_out, void *stream)
+{
+    if (!c || (count && (!d_n || !d_out)))
+        return SIEVE_EINVAL;
+    if (count == 0)
+        return SIEVE_OK;
+    SV_HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
+    const uint64_t want = (count + 255) / 256;
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 64ull * c->n_cu));
+    c->ev_valid = false;
+    SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    SV_HIP_TRY(c, sv::launch_is_prime(d_n, count, d_out, blocks, s));
+    SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+    c->ev_valid = true;
+    return SIEVE_OK;
+}
+
+int sieve_fermat_batch(sieve_ctx *c, const uint64_t *d_n, uint64_t count, const uint64_t *d_draws,
+                       uint32_t iterations, uint8_t *d_out, void *stream)
+{
+    if (!c || (count && (!d_n || !d_out)) || (iterations && !d_draws))
+        return SIEVE_EINVAL;
+    if (count == 0)
+        return SIEVE_OK;
+    SV_HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
+    const uint64_t want = (count + 255) / 256;
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 64ull * c->n_cu));
+    c->ev_valid = false;
+    SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    SV_HIP_TRY(c, sv::launch_fermat(d_n, count, d_draws, iterations, d_out, blocks, s));
+    SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+    c->ev_valid = true;
+    return SIEVE_OK;
+}
+
+}  // extern "C"

@@ -2,6 +2,9 @@
 // loop (sieve_serve.hip).  Not part of the public ABI.
 #pragma once
 
+#include <algorithm>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "sieve.h"
@@ -90,6 +93,9 @@ struct sieve_ctx {
     bool ev_valid = false;
 
     sv::BatchEngine batch;
+
+    // autotuner cache: (batch?, decade of max hi, log2 of total words)
+    std::map<std::tuple<int, int, int>, std::pair<sieve_tuning, double>> tune_cache;
 };
 
 namespace sv {
@@ -127,6 +133,10 @@ void engine_free(BatchEngine &e);
 int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                  uint64_t total_words);
 int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed);
+hipError_t launch_is_prime(const uint64_t *d_n, uint64_t count, uint8_t *d_out, uint32_t blocks, hipStream_t s);
+hipError_t launch_fermat(const uint64_t *d_n, uint64_t count, const uint64_t *d_draws, uint32_t iterations,
+                         uint8_t *d_out, uint32_t blocks, hipStream_t s);
+
 inline const unsigned long long *counts_host(const BatchEngine &e)
 {
     return static_cast<const unsigned long long *>(e.s_counts.p);

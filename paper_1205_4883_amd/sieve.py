@@ -29,6 +29,7 @@ EXPORTED = [
     "sieve_last_kernel_ms",
     "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
     "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
+    "sieve_autotune", "sieve_is_prime_batch", "sieve_fermat_batch",
     "sieve_server_create", "sieve_server_submit", "sieve_server_poll", "sieve_server_release",
     "sieve_server_get_stats", "sieve_server_destroy", "sieve_serve_trace",
 ]
@@ -118,6 +119,10 @@ def _lib():
     lib.sieve_range_count.argtypes = [vp, u64, u64, u64p, vp]
     lib.sieve_range_bitmap.argtypes = [vp, u64, u64, vp, u64, u64p, vp]
     lib.sieve_batch.argtypes = [vp, vp, u32, vp, u64, vp, vp]
+    lib.sieve_is_prime_batch.argtypes = [vp, vp, u64, vp, vp]
+    lib.sieve_fermat_batch.argtypes = [vp, vp, u64, vp, u32, vp, vp]
+    lib.sieve_autotune.argtypes = [vp, vp, u32, u32, ctypes.POINTER(sieve_tuning),
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.sieve_server_create.argtypes = [i32, ctypes.POINTER(sieve_server_config), ctypes.POINTER(vp)]
     lib.sieve_server_submit.argtypes = [vp, u64, u64, u32, u64p]
     lib.sieve_server_poll.argtypes = [vp, ctypes.POINTER(sieve_result), u32, ctypes.POINTER(u32), u32]
@@ -227,6 +232,44 @@ def sieve_batch(ctx, intervals, d_words=None, total_words=0, stream=None):
     _check(_lib().sieve_batch(ctx, iv.ctypes.data, len(iv), ctypes.c_void_p(ptr), total_words,
                               pi.ctypes.data, _stream_ptr(stream)), "sieve_batch")
     return pi[: len(iv)]
+
+
+def _ptr(x):
+    return x.data_ptr() if hasattr(x, "data_ptr") else (x or 0)
+
+
+def sieve_is_prime_batch(ctx, d_n, count, d_out, stream=None):
+    """Device arrays: d_n uint64[count] -> d_out uint8[count] (1 = prime)."""
+    _check(_lib().sieve_is_prime_batch(ctx, ctypes.c_void_p(_ptr(d_n)), count,
+                                       ctypes.c_void_p(_ptr(d_out)), _stream_ptr(stream)),
+           "sieve_is_prime_batch")
+
+
+def sieve_fermat_batch(ctx, d_n, count, d_draws, iterations, d_out, stream=None):
+    """Alg. 3 on device arrays, with the caller's random draws."""
+    _check(_lib().sieve_fermat_batch(ctx, ctypes.c_void_p(_ptr(d_n)), count,
+                                     ctypes.c_void_p(_ptr(d_draws)), iterations,
+                                     ctypes.c_void_p(_ptr(d_out)), _stream_ptr(stream)),
+           "sieve_fermat_batch")
+
+
+SIEVE_TUNE_APPLY = 1
+SIEVE_TUNE_FORCE = 2
+
+
+def sieve_autotune(ctx, los, his, apply=True, force=False):
+    """Time candidate tunings on the ranges [los[i], his[i]); returns
+    (tuning dict, kernel ms of the winner)."""
+    los = np.atleast_1d(np.asarray(los, dtype=np.uint64))
+    his = np.atleast_1d(np.asarray(his, dtype=np.uint64))
+    iv = np.zeros(len(los), dtype=INTERVAL_DTYPE)
+    iv["lo"], iv["hi"] = los, his
+    t = sieve_tuning()
+    ms = ctypes.c_double(0)
+    flags = (SIEVE_TUNE_APPLY if apply else 0) | (SIEVE_TUNE_FORCE if force else 0)
+    _check(_lib().sieve_autotune(ctx, iv.ctypes.data, len(iv), flags, ctypes.byref(t),
+                                 ctypes.byref(ms)), "sieve_autotune")
+    return {k: getattr(t, k) for k, _ in sieve_tuning._fields_}, ms.value
 
 
 def _server_config(cfg):
@@ -368,6 +411,26 @@ class Sieve:
 
     def base_primes(self, limit):
         return sieve_base_primes(self.ctx, limit)
+
+    def _u64_tensor(self, ns):
+        arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64))
+        t = self.torch.from_numpy(arr.view(np.int64)).to(f"cuda:{self.device}")
+        return arr, t
+
+    def is_prime(self, ns):
+        """numpy bool array: primality of each uint64 in ns (on the GPU)."""
+        arr, d_n = self._u64_tensor(ns)
+        out = self.torch.empty(max(1, arr.size), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        sieve_is_prime_batch(self.ctx, d_n, arr.size, out, stream=self._stream())
+        return out[: arr.size].cpu().numpy().astype(bool)
+
+    def fermat(self, ns, draws):
+        """numpy bool array: the Fermat test (Alg. 3) of each n with the given draws."""
+        arr, d_n = self._u64_tensor(ns)
+        _, d_draws = self._u64_tensor(draws if len(draws) else [0])
+        out = self.torch.empty(max(1, arr.size), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        sieve_fermat_batch(self.ctx, d_n, arr.size, d_draws, len(draws), out, stream=self._stream())
+        return out[: arr.size].cpu().numpy().astype(bool)
 
     def count(self, lo, hi):
         return sieve_range_count(self.ctx, lo, hi, stream=self._stream())
