@@ -69,10 +69,15 @@ typedef struct sieve_ctx sieve_ctx;
  *   dense_limit   base primes below this are marked by a whole wavefront per
  *                 prime (64 lanes on 64 consecutive multiples); primes at or
  *                 above it by one lane per prime.  Clamped to >= 37.
- *   bucket_limit  base primes at or above this are not scanned per segment:
- *                 their hits are first sorted into per-segment buckets in HBM
- *                 (batched and plain paths).  0 = never use buckets.
- *   bucket_depth  entries per segment bucket (0 = automatic).
+ *   bucket_limit  base primes at or above this (and at least seg_bits) are
+ *                 not scanned per segment: a fill kernel first sorts their
+ *                 hits into per-segment buckets in HBM, which the segment
+ *                 kernel then applies (plain path).  0 = automatic (buckets
+ *                 when sqrt(hi) >= 2 * seg_bits), 0xFFFFFFFF = never.
+ *   bucket_depth  entries per segment bucket (0 = from the expected hits
+ *                 plus six standard deviations).  A bucket that overflows is
+ *                 detected and the call is redone with twice the depth, so
+ *                 results never depend on it.
  *   block_threads threads per workgroup: 256, 512 or 1024.
  *   wg_per_cu     resident workgroups per compute unit for persistent
  *                 launches (0 = as many as LDS allows). */
@@ -94,7 +99,7 @@ typedef struct sieve_plan_info {
     uint32_t seg_bits;     /* odd integers per segment (tuning resolved) */
     uint32_t dense_limit;  /* resolved */
     uint32_t block_threads;/* resolved */
-    uint32_t pad;
+    uint32_t bucket_limit; /* resolved: primes >= this use hit buckets, 0 = none */
 } sieve_plan_info;
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the

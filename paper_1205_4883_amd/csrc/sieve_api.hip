@@ -51,7 +51,7 @@ int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
     if (t.block_threads && t.block_threads != 256 && t.block_threads != 512 &&
         t.block_threads != 1024)
         return SIEVE_EINVAL;
-    if (t.bucket_limit != 0 || t.bucket_depth != 0)  // bucket path not built
+    if (t.bucket_depth > (1u << 24))
         return SIEVE_EINVAL;
     if (t.wg_per_cu > 16)
         return SIEVE_EINVAL;
@@ -83,16 +83,29 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     if (t.seg_bits) {
         sw = t.seg_bits / 32;
     } else {
-        // enough segments for two workgroups per CU, within the LDS cap
-        uint64_t want = (p.n_words + 2ull * n_cu - 1) / (2ull * n_cu);
-        want = (want + kSegGranuleWords - 1) / kSegGranuleWords * kSegGranuleWords;
-        sw = static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(want, kSegGranuleWords), cap));
+        // enough segments for two workgroups per CU, within the LDS cap; a
+        // power of two, so that hit buckets can split offsets with shifts
+        const uint64_t want = (p.n_words + 2ull * n_cu - 1) / (2ull * n_cu);
+        uint64_t pw = kSegGranuleWords;
+        while (pw < want && pw < cap)
+            pw *= 2;
+        sw = static_cast<uint32_t>(std::min<uint64_t>(pw, cap));
     }
     p.seg_bits = sw * 32;
     p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 512;
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
     p.block_threads = t.block_threads ? t.block_threads : (sw >= 2048 ? 512u : 256u);
     p.n_segments = (p.n_words + sw - 1) / sw;
+    // Hit buckets need power-of-two segments and only pay when the largest
+    // base primes skip most segments.
+    p.bucket_limit = 0;
+    const bool pow2 = (p.seg_bits & (p.seg_bits - 1)) == 0;
+    if (t.bucket_limit != 0xffffffffu && pow2 && p.n_segments >= 2) {
+        const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
+        const bool want = t.bucket_limit ? true : p.sqrt_bound >= 2ull * p.seg_bits;
+        if (want && lim <= p.sqrt_bound && lim < 0xffffffffull)
+            p.bucket_limit = static_cast<uint32_t>(lim);
+    }
     *out = p;
     return SIEVE_OK;
 }
@@ -184,7 +197,7 @@ int build_primes(sieve_ctx *c, uint64_t limit)
             break;
         }
         uint32_t *queue = reinterpret_cast<uint32_t *>(slot + 1);
-        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr, queue};
+        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr, queue, nullptr, nullptr, 0};
         e = hipMemsetAsync(queue, 0, sizeof(uint32_t), s);
         if (e != hipSuccess) {
             c->last_hip = e;
@@ -242,6 +255,9 @@ int build_primes(sieve_ctx *c, uint64_t limit)
         d_out = nullptr;
         d_out_inv = nullptr;
         c->h_primes.swap(h);
+        c->h_recip_prefix.assign(c->h_primes.size() + 1, 0.0);
+        for (size_t i = 0; i < c->h_primes.size(); ++i)
+            c->h_recip_prefix[i + 1] = c->h_recip_prefix[i] + 1.0 / c->h_primes[i];
         c->primes_limit = limit;
     } while (false);
     (void)hipFree(d_boot);
@@ -281,6 +297,94 @@ void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32
     *n_dense = std::min(*n_mark, nd > sv::kPresievePrimes ? nd - sv::kPresievePrimes : 0u);
 }
 
+namespace {
+
+// The plain path with large-prime hit buckets: the range is cut into
+// windows of W segments (the bucket pool holds W buckets); per window, the
+// fill kernel sorts the large primes' hits into buckets, then the range
+// kernel sieves the window's segments with the small and medium primes plus
+// its buckets.  Counts accumulate in the call's slot.  An overflowing bucket
+// is detected after the last window and the call is redone with twice the
+// depth.
+int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uint32_t *d_words,
+                       uint64_t *pi_out, hipStream_t s, uint32_t n_mark, uint32_t n_dense)
+{
+    const auto &v = c->h_primes;
+    const uint32_t sw = pl.seg_bits / 32;
+    uint32_t seg_log2 = 0;
+    while ((1u << seg_log2) < pl.seg_bits)
+        ++seg_log2;
+    // marking primes [0, n_small) are scanned per segment; [n_small, n_mark) are bucketed
+    const uint32_t n_below = static_cast<uint32_t>(std::lower_bound(v.begin(), v.end(), pl.bucket_limit) - v.begin());
+    const uint32_t n_small = std::min(n_mark, n_below > kPresievePrimes ? n_below - kPresievePrimes : 0u);
+    const uint32_t n_large = n_mark - n_small;
+    // expected hits per segment: (8/15) * (seg_bits / p) summed over the large primes
+    const double recip = c->h_recip_prefix[kPresievePrimes + n_mark] - c->h_recip_prefix[kPresievePrimes + n_small];
+    const double expect = (8.0 / 15.0) * pl.seg_bits * recip;
+    uint64_t depth = c->tuning.bucket_depth
+                         ? c->tuning.bucket_depth
+                         : static_cast<uint64_t>(expect + 6.0 * std::sqrt(expect) + 64.0);
+    depth = (depth + 63) / 64 * 64;
+    const uint64_t first_odd = (lo & ~1ull) + 1;
+    for (;;) {
+        const uint64_t win = std::max<uint64_t>(1, std::min<uint64_t>(pl.n_segments, kBucketPoolBytes / (4 * depth)));
+        if (int st = grow(c, c->b_buckets, win * depth * sizeof(uint32_t)))
+            return st;
+        if (int st = grow(c, c->b_bcount, (win + 1) * sizeof(uint32_t)))
+            return st;
+        uint32_t *buckets = static_cast<uint32_t *>(c->b_buckets.p);
+        uint32_t *bcount = static_cast<uint32_t *>(c->b_bcount.p);
+        uint32_t *overflow = bcount + win;
+        unsigned long long *slot = nullptr;
+        const int si = take_slot(c, &slot);
+        if (si < 0)
+            return si;
+        uint32_t *queue = reinterpret_cast<uint32_t *>(slot + 1);
+        HIP_TRY(c, hipMemsetAsync(slot, 0, 2 * sizeof(unsigned long long), s));
+        HIP_TRY(c, hipMemsetAsync(overflow, 0, sizeof(uint32_t), s));
+        c->ev_valid = false;
+        HIP_TRY(c, hipEventRecord(c->ev_start, s));
+        for (uint64_t w0 = 0; w0 < pl.n_segments; w0 += win) {
+            const uint32_t segs = static_cast<uint32_t>(std::min<uint64_t>(win, pl.n_segments - w0));
+            const uint64_t word0 = w0 * sw;
+            const uint64_t bits_w = std::min<uint64_t>(static_cast<uint64_t>(segs) * pl.seg_bits, pl.nbits - word0 * 32);
+            const uint64_t fo = first_odd + 64 * word0;
+            HIP_TRY(c, hipMemsetAsync(bcount, 0, segs * sizeof(uint32_t), s));
+            HIP_TRY(c, hipMemsetAsync(queue, 0, sizeof(uint32_t), s));
+            HIP_TRY(c, sv::launch_bucket_fill(c->d_primes + kPresievePrimes + n_small,
+                                              c->d_inv + kPresievePrimes + n_small, n_large, fo, seg_log2, segs,
+                                              buckets, bcount, static_cast<uint32_t>(depth), overflow, s));
+            sv::RangeArgs ra{fo, bits_w, (bits_w + 31) / 32, d_words ? d_words + word0 : nullptr,
+                             pi_out ? slot : nullptr, queue, buckets, bcount, static_cast<uint32_t>(depth)};
+            sv::PrimeArgs pa{c->d_primes + kPresievePrimes, c->d_inv + kPresievePrimes, std::min(n_dense, n_small),
+                             n_small};
+            sieve_plan_info wp = pl;
+            wp.n_segments = segs;
+            HIP_TRY(c, sv::launch_range(ra, pa, sw, pl.block_threads, segs,
+                                        resident_blocks(c, wp, d_words != nullptr), s));
+        }
+        HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+        c->ev_valid = true;
+        uint32_t *h_flag = reinterpret_cast<uint32_t *>(c->h_count + 1);
+        if (pi_out)
+            HIP_TRY(c, hipMemcpyAsync(c->h_count, slot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(h_flag, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
+        c->slot_used[si] = true;
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (*h_flag == 0) {
+            if (pi_out)
+                *pi_out = *c->h_count;  // odd primes only
+            return SIEVE_OK;
+        }
+        if (depth >= (1ull << 26))
+            return SIEVE_EOVERFLOW;
+        depth *= 2;
+    }
+}
+
+}  // namespace
+
 int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t *pi_out,
               hipStream_t s)
 {
@@ -300,12 +404,20 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
         return st;
     uint32_t n_mark = 0, n_dense = 0;
     marking_primes(c, pl.sqrt_bound, pl.dense_limit, &n_mark, &n_dense);
+    if (pl.bucket_limit) {
+        uint64_t pi = 0;
+        if (int st = run_range_bucketed(c, pl, lo, d_words, pi_out ? &pi : nullptr, s, n_mark, n_dense))
+            return st;
+        if (pi_out)
+            *pi_out = pi + two;
+        return SIEVE_OK;
+    }
     unsigned long long *slot = nullptr;
     const int si = take_slot(c, &slot);
     if (si < 0)
         return si;
     sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, pi_out ? slot : nullptr,
-                     reinterpret_cast<uint32_t *>(slot + 1)};
+                     reinterpret_cast<uint32_t *>(slot + 1), nullptr, nullptr, 0};
     sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
     HIP_TRY(c, hipMemsetAsync(slot, 0, 2 * sizeof(unsigned long long), s));
     c->ev_valid = false;
@@ -662,7 +774,7 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
     for (int i = 0; i < sieve_ctx::kSlots && e == hipSuccess; ++i)
         e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
     if (e == hipSuccess)
-        e = hipHostMalloc(&c->h_count, sizeof(unsigned long long), hipHostMallocDefault);
+        e = hipHostMalloc(&c->h_count, 2 * sizeof(unsigned long long), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess)
@@ -691,6 +803,9 @@ int sieve_destroy(sieve_ctx *c)
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
     sv::engine_free(c->batch);
+    for (sv::DevBuf *b : {&c->b_buckets, &c->b_bcount})
+        if (b->p)
+            (void)hipFree(b->p);
     if (c->d_primes)
         (void)hipFree(c->d_primes);
     if (c->d_inv)

@@ -27,6 +27,12 @@ struct RangeArgs {
     uint32_t *out;       // bitmap words of the range (word 0 = bit 0), or null
     unsigned long long *count;  // += number of 1 bits (primes), or null
     uint32_t *queue;     // segment counter, zero at launch
+    // Large-prime hit buckets of this launch's segments, or null: segment s
+    // owns buckets[s * bucket_depth ..) with min(bucket_count[s], depth)
+    // entries, each a bit offset inside the segment.
+    const uint32_t *buckets;
+    const uint32_t *bucket_count;
+    uint32_t bucket_depth;
 };
 
 // The marking primes of one launch: odd primes >= 37, ascending.
@@ -69,6 +75,16 @@ hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream
 hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_segments, uint32_t max_blocks,
                         hipStream_t s);
+
+// Bucket fill: the hits of primes[0, n_large) (all >= the segment size) on
+// the n_segs segments of 2^seg_log2 bits starting at the odd integer
+// first_odd, in chunks of kBucketChunk segments.  Appends bit offsets to
+// buckets[s * depth ..), counting in bucket_count[s] (zero at launch); sets
+// *overflow when a segment needs more than depth entries.
+constexpr uint32_t kBucketChunk = 32;
+hipError_t launch_bucket_fill(const uint32_t *primes, const double *inv, uint32_t n_large,
+                              uint64_t first_odd, uint32_t seg_log2, uint32_t n_segs, uint32_t *buckets,
+                              uint32_t *bucket_count, uint32_t depth, uint32_t *overflow, hipStream_t s);
 
 // inv[i] = 1.0 / primes[i] for i < n.
 hipError_t launch_reciprocals(const uint32_t *d_primes, uint32_t n, double *d_inv, hipStream_t s);

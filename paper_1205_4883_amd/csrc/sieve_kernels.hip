@@ -250,7 +250,9 @@ template <bool kWrite>
 __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
                               uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
                               const uint32_t *primes, const double *inv, uint32_t n_dense,
-                              uint32_t n_primes, uint32_t *out, unsigned long long *count)
+                              uint32_t n_primes, uint32_t *out, unsigned long long *count,
+                              const uint32_t *buckets = nullptr, const uint32_t *bucket_count = nullptr,
+                              uint32_t bucket_depth = 0)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
@@ -315,6 +317,15 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
         const Start st = first_multiple(n0, nf, p, inv[i], lim_bits);
         mark_sparse(seg_lds, lim_bits, p, st.off, st.m30);
     }
+    // 2c. large primes: the segment's bucket of precomputed hits.
+    if (buckets) {
+        const uint32_t nb = min(bucket_count[seg], bucket_depth);
+        const uint32_t *bk = buckets + seg * bucket_depth;
+        for (uint32_t e = t; e < nb; e += nthreads) {
+            const uint32_t b = bk[e];
+            lds_or(seg_lds + (b >> 5), 1u << (b & 31));
+        }
+    }
     __syncthreads();
 
     // 3. count (and store) the unmarked bits.
@@ -361,7 +372,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         if (s >= n_segments)
             break;
         sieve_segment<kWrite>(tabs, seg, seg_words, s, r.first_odd, r.nbits, r.n_words, pa.primes,
-                              pa.inv, pa.n_dense, pa.n_primes, r.out, r.count);
+                              pa.inv, pa.n_dense, pa.n_primes, r.out, r.count, r.buckets, r.bucket_count,
+                              r.bucket_depth);
     }
 }
 
@@ -560,6 +572,70 @@ __global__ void __launch_bounds__(kCompactThreads) compact_write_kernel(const ui
     }
 }
 
+// Walk the wheel-30 multiples of one large prime over one chunk, calling
+// hit(off) for each bit offset off < chunk_bits.
+template <typename F>
+__device__ __forceinline__ void walk_hits(uint64_t n0, uint32_t p, double inv, uint32_t chunk_bits, F hit)
+{
+    const Start st = first_multiple(n0, static_cast<double>(n0), p, inv, chunk_bits);
+    uint32_t o = st.off, m30 = st.m30;
+    while (((kWheelMask >> m30) & 1u) == 0) {
+        m30 += 2;
+        o += p;
+    }
+    const uint32_t idx = __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;
+    uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
+    while (o < chunk_bits) {
+        hit(o);
+        o += (g & 3u) * p;
+        g = __builtin_amdgcn_alignbit(g, g, 2);
+    }
+}
+
+// One workgroup: a chunk of kBucketChunk segments (blockIdx.y) against 256
+// large primes (blockIdx.x).  Two passes over the same hits: the first
+// counts them per segment in LDS, then one global atomic per segment
+// reserves room in its bucket, and the second writes each hit at its rank.
+__global__ void __launch_bounds__(256) bucket_fill_kernel(const uint32_t *primes, const double *inv,
+                                                          uint32_t n_large, uint64_t first_odd, uint32_t seg_log2,
+                                                          uint32_t n_segs, uint32_t *buckets, uint32_t *bucket_count,
+                                                          uint32_t depth, uint32_t *overflow)
+{
+    __shared__ uint32_t cnt[kBucketChunk];
+    __shared__ uint32_t base[kBucketChunk];
+    const uint32_t t = threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + t;
+    const uint32_t seg0 = blockIdx.y * kBucketChunk;
+    const uint32_t segs = min(kBucketChunk, n_segs - seg0);
+    const uint32_t chunk_bits = segs << seg_log2;
+    const uint64_t n0 = first_odd + (static_cast<uint64_t>(seg0) << (seg_log2 + 1));
+    if (t < kBucketChunk)
+        cnt[t] = 0;
+    __syncthreads();
+    const bool live = i < n_large;
+    const uint32_t p = live ? primes[i] : 0;
+    const double pinv = live ? inv[i] : 0.0;
+    if (live)
+        walk_hits(n0, p, pinv, chunk_bits, [&](uint32_t o) { atomicAdd(&cnt[o >> seg_log2], 1u); });
+    __syncthreads();
+    if (t < segs) {
+        base[t] = atomicAdd(&bucket_count[seg0 + t], cnt[t]);
+        cnt[t] = 0;
+    }
+    __syncthreads();
+    if (live) {
+        const uint32_t mask = (1u << seg_log2) - 1u;
+        walk_hits(n0, p, pinv, chunk_bits, [&](uint32_t o) {
+            const uint32_t s = o >> seg_log2;
+            const uint32_t slot = base[s] + atomicAdd(&cnt[s], 1u);
+            if (slot < depth)
+                buckets[static_cast<uint64_t>(seg0 + s) * depth + slot] = o & mask;
+            else
+                atomicOr(overflow, 1u);
+        });
+    }
+}
+
 __global__ void __launch_bounds__(256) reciprocal_kernel(const uint32_t *primes, uint32_t n, double *inv)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -594,6 +670,18 @@ uint32_t max_seg_words()
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s)
 {
     hipLaunchKernelGGL(bootstrap_kernel, dim3(1), dim3(1024), 0, s, d_out, d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_fill(const uint32_t *primes, const double *inv, uint32_t n_large,
+                              uint64_t first_odd, uint32_t seg_log2, uint32_t n_segs, uint32_t *buckets,
+                              uint32_t *bucket_count, uint32_t depth, uint32_t *overflow, hipStream_t s)
+{
+    if (n_large == 0 || n_segs == 0)
+        return hipSuccess;
+    const dim3 grid((n_large + 255) / 256, (n_segs + kBucketChunk - 1) / kBucketChunk);
+    hipLaunchKernelGGL(bucket_fill_kernel, grid, dim3(256), 0, s, primes, inv, n_large, first_odd, seg_log2,
+                       n_segs, buckets, bucket_count, depth, overflow);
     return hipGetLastError();
 }
 

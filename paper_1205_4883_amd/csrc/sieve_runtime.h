@@ -17,6 +17,7 @@ constexpr uint64_t kDefaultPrimeLimit = 1u << 20;  // covers hi <= 1.0995e12
 constexpr uint32_t kSegGranuleWords = 128;         // 4096 bits
 constexpr uint32_t kDefaultMaxSegWords = 16384;    // 2^19 bits = 64 KiB of LDS
 constexpr uint64_t kDefaultBudget = 32ull << 30;
+constexpr uint64_t kBucketPoolBytes = 256ull << 20;  // bucket memory per window of segments
 
 struct DevBuf {
     void *p = nullptr;
@@ -75,6 +76,7 @@ struct sieve_ctx {
     // base primes: all odd primes <= primes_limit, ascending
     uint64_t primes_limit = 0;
     std::vector<uint32_t> h_primes;
+    std::vector<double> h_recip_prefix;  // sum of 1/p over h_primes[0, i)
     uint32_t *d_primes = nullptr;
     double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
 
@@ -93,6 +95,9 @@ struct sieve_ctx {
     bool ev_valid = false;
 
     sv::BatchEngine batch;
+
+    // large-prime hit buckets of the plain path (grown on demand)
+    sv::DevBuf b_buckets, b_bcount;
 
     // autotuner cache: (batch?, decade of max hi, log2 of total words)
     std::map<std::tuple<int, int, int>, std::pair<sieve_tuning, double>> tune_cache;

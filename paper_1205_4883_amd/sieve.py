@@ -48,7 +48,7 @@ class sieve_plan_info(ctypes.Structure):
     _fields_ = [("nbits", ctypes.c_uint64), ("n_words", ctypes.c_uint64),
                 ("sqrt_bound", ctypes.c_uint64), ("n_segments", ctypes.c_uint64),
                 ("seg_bits", ctypes.c_uint32), ("dense_limit", ctypes.c_uint32),
-                ("block_threads", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("block_threads", ctypes.c_uint32), ("bucket_limit", ctypes.c_uint32)]
 
 
 class sieve_interval(ctypes.Structure):
@@ -184,7 +184,7 @@ def sieve_plan(lo, hi, tuning=None, n_cu=256, lds_bytes=163840):
     info = sieve_plan_info()
     t = ctypes.byref(sieve_tuning(**tuning)) if tuning else None
     _check(_lib().sieve_plan(lo, hi, t, n_cu, lds_bytes, ctypes.byref(info)), "sieve_plan")
-    return {k: getattr(info, k) for k, _ in sieve_plan_info._fields_ if k != "pad"}
+    return {k: getattr(info, k) for k, _ in sieve_plan_info._fields_}
 
 
 def sieve_bitmap_words(lo, hi):

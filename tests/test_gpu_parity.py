@@ -307,3 +307,37 @@ def test_batch_workload_counts(gpu, oracle_mod):
     pi = gpu.batch(los, his, want_bitmap=False)
     for i in range(len(los)):
         assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), i
+
+
+# -- large-prime hit buckets ---------------------------------------------------
+
+@pytest.mark.parametrize("lo,hi,seg_bits,limit,depth", [
+    (10**12, 10**12 + 5 * 10**7, 65536, 65536, 0),       # forced buckets, auto depth
+    (10**12 + 1, 10**12 + 3 * 10**7 + 7, 65536, 131072, 0),
+    (10**12, 10**12 + 2 * 10**7, 65536, 65536, 64),      # tiny depth: overflow, retry
+    (10**13 - 3, 10**13 + 2 * 10**7, 131072, 0, 0),      # automatic choice
+    (10**15 - 4 * 10**7, 10**15, 0, 0, 0),               # automatic at the top of the domain
+])
+def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth):
+    gpu.tuning(seg_bits=seg_bits, bucket_limit=limit, bucket_depth=depth)
+    try:
+        plan = sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())
+        if limit or hi >= 10**15:
+            assert plan["bucket_limit"] > 0
+        _cmp_bitmap(gpu, oracle_mod, lo, hi)
+    finally:
+        gpu.tuning(seg_bits=0, bucket_limit=0, bucket_depth=0)
+
+
+def test_buckets_off_and_on_agree(gpu, sv_mod):
+    lo, hi = 10**14, 10**14 + 6 * 10**7
+    gpu.tuning(bucket_limit=0xFFFFFFFF)
+    try:
+        assert sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())["bucket_limit"] == 0
+        w0, p0 = gpu.bitmap(lo, hi)
+        a = w0.cpu().numpy()
+    finally:
+        gpu.tuning(bucket_limit=0)
+    assert sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())["bucket_limit"] > 0
+    w1, p1 = gpu.bitmap(lo, hi)
+    assert p0 == p1 and np.array_equal(a, w1.cpu().numpy())
