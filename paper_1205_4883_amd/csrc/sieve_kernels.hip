@@ -53,15 +53,6 @@ constexpr uint32_t kWheelGaps16 = 3u | (2u << 2) | (1u << 4) | (2u << 6) | (1u <
                                   (3u << 12) | (1u << 14);
 constexpr uint32_t kWheelGaps = kWheelGaps16 | (kWheelGaps16 << 16);
 
-// a * b + c with a, b < 2^24: one full-rate VALU op (the compiler would
-// otherwise pick a 64-bit multiply-add for a 32-bit product).
-__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c)
-{
-    uint32_t d;
-    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-
 __device__ __forceinline__ void lds_or(uint32_t *word, uint32_t mask)
 {
     __hip_atomic_fetch_or(word, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -195,6 +186,9 @@ __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t 
 
 // Sparse marking of one prime by one lane: the multiples p*m with m prime to
 // 15, from the segment's first odd multiple (bit offset o, m mod 30 = m30).
+// The eight offsets of one turn of the wheel (15 odd steps, 15p bits) are
+// computed once, so a mark inside a full turn costs one add plus the
+// address and mask; the last partial turn is guarded mark by mark.
 __device__ __forceinline__ void mark_sparse(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
                                             uint32_t m30)
 {
@@ -204,19 +198,27 @@ __device__ __forceinline__ void mark_sparse(uint32_t *seg, uint32_t lim_bits, ui
         o += p;
     }
     const uint32_t idx = __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;  // position in the cycle
-    uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
-    if (p < (1u << 24)) {  // gap * p as a full-rate 24-bit multiply-add
-        while (o < lim_bits) {
-            lds_or(seg + (o >> 5), 1u << (o & 31));
-            o = mad_u24(g & 3u, p, o);
-            g = __builtin_amdgcn_alignbit(g, g, 2);
+    const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
+    uint32_t d[8];
+    d[0] = 0;
+#pragma unroll
+    for (int j = 1; j < 8; ++j)
+        d[j] = d[j - 1] + ((g >> (2 * (j - 1))) & 3u) * p;
+    const uint32_t turn = 15 * p;
+    uint32_t base = o;
+    for (; base + d[7] < lim_bits; base += turn) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t x = base + d[j];
+            lds_or(seg + (x >> 5), 1u << (x & 31));
         }
-    } else {
-        while (o < lim_bits) {
-            lds_or(seg + (o >> 5), 1u << (o & 31));
-            o += (g & 3u) * p;
-            g = __builtin_amdgcn_alignbit(g, g, 2);
-        }
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const uint32_t x = base + d[j];
+        if (x >= lim_bits)
+            break;
+        lds_or(seg + (x >> 5), 1u << (x & 31));
     }
 }
 
@@ -328,19 +330,24 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
     }
     __syncthreads();
 
-    // 3. count (and store) the unmarked bits.
+    // 3. count (and store) the unmarked bits.  Only the range's first word
+    //    (small primes, 1) and last word (tail bits) need fixing; both are
+    //    patched in LDS by one thread before the sweep.
+    if (t == 0) {
+        if (w0 == 0)
+            seg_lds[0] = ~fix_first_word(~seg_lds[0], first_odd);
+        const uint32_t tail = static_cast<uint32_t>(nbits & 31);
+        if (tail && w0 + sw == n_words)
+            seg_lds[sw - 1] |= ~((1u << tail) - 1);
+    }
+    __syncthreads();
     uint32_t c = 0;
-    const uint32_t tail = static_cast<uint32_t>(nbits & 31);
+    uint32_t *o = kWrite ? out + w0 : nullptr;
     for (uint32_t w = t; w < sw; w += nthreads) {
-        uint32_t v = ~seg_lds[w];
-        const uint64_t gw = w0 + w;
-        if (gw == 0)
-            v = fix_first_word(v, first_odd);
-        if (tail && gw == n_words - 1)
-            v &= (1u << tail) - 1;
+        const uint32_t v = ~seg_lds[w];
         c += __popc(v);
         if (kWrite)
-            out[gw] = v;
+            o[w] = v;
     }
     c = wave_sum(c);
     if ((t & 63) == 0 && count)
