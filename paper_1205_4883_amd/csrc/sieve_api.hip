@@ -58,6 +58,14 @@ int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
     return SIEVE_OK;
 }
 
+// Workgroup size for a segment of sw words: more waves share a larger
+// segment's marking work (measured best: 1024 threads from 2^19 bits, 512
+// from 2^16, 256 below).
+uint32_t default_threads(uint32_t sw)
+{
+    return sw >= 16384 ? 1024u : (sw >= 2048 ? 512u : 256u);
+}
+
 int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
               sieve_plan_info *out)
 {
@@ -94,7 +102,7 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.seg_bits = sw * 32;
     p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 512;
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
-    p.block_threads = t.block_threads ? t.block_threads : (sw >= 2048 ? 512u : 256u);
+    p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
     // Hit buckets need power-of-two segments and only pay when the largest
     // base primes skip most segments.
@@ -110,16 +118,34 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     return SIEVE_OK;
 }
 
-// The next per-call {count, queue} slot, once its previous user has finished.
-int take_slot(sieve_ctx *c, unsigned long long **words)
+// The next per-call counter slot, once its previous user has finished.
+int take_slot(sieve_ctx *c, uint32_t **words)
 {
     const int i = c->next_slot;
     c->next_slot = (i + 1) % sieve_ctx::kSlots;
     if (c->slot_used[i])
         HIP_TRY(c, hipEventSynchronize(c->slot_done[i]));
     c->slot_used[i] = false;
-    *words = c->d_count + 2 * i;
+    *words = c->d_ctr + static_cast<size_t>(i) * kCounterWords;
     return i;
+}
+
+constexpr size_t kQueueBytes = kQueues * kLineWords * sizeof(uint32_t);  // the queue lines of a slot
+constexpr size_t kCountBytes = kQueueBytes;                              // the count lines
+
+// Copy a slot's count lines to the pinned mirror (asynchronous on s).
+hipError_t fetch_counts(sieve_ctx *c, const uint32_t *slot, hipStream_t s)
+{
+    return hipMemcpyAsync(c->h_ctr, slot + kQueues * kLineWords, kCountBytes, hipMemcpyDeviceToHost, s);
+}
+
+// Sum of the partial counts in the pinned mirror (once the copy completed).
+uint64_t mirrored_count(const sieve_ctx *c)
+{
+    uint64_t total = 0;
+    for (uint32_t q = 0; q < kQueues; ++q)
+        total += *reinterpret_cast<const uint64_t *>(c->h_ctr + q * kLineWords);
+    return total;
 }
 
 // Workgroups that fit on the device at once for a plan.
@@ -190,15 +216,14 @@ int build_primes(sieve_ctx *c, uint64_t limit)
             st = SIEVE_ENOMEM;
             break;
         }
-        unsigned long long *slot = nullptr;
+        uint32_t *slot = nullptr;
         const int si = take_slot(c, &slot);
         if (si < 0) {
             st = si;
             break;
         }
-        uint32_t *queue = reinterpret_cast<uint32_t *>(slot + 1);
-        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, nullptr, queue, nullptr, nullptr, 0};
-        e = hipMemsetAsync(queue, 0, sizeof(uint32_t), s);
+        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, slot, false, nullptr, nullptr, 0};
+        e = hipMemsetAsync(slot, 0, kQueueBytes, s);
         if (e != hipSuccess) {
             c->last_hip = e;
             st = SIEVE_EDEVICE;
@@ -335,12 +360,11 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
         uint32_t *buckets = static_cast<uint32_t *>(c->b_buckets.p);
         uint32_t *bcount = static_cast<uint32_t *>(c->b_bcount.p);
         uint32_t *overflow = bcount + win;
-        unsigned long long *slot = nullptr;
+        uint32_t *slot = nullptr;
         const int si = take_slot(c, &slot);
         if (si < 0)
             return si;
-        uint32_t *queue = reinterpret_cast<uint32_t *>(slot + 1);
-        HIP_TRY(c, hipMemsetAsync(slot, 0, 2 * sizeof(unsigned long long), s));
+        HIP_TRY(c, hipMemsetAsync(slot + kQueues * kLineWords, 0, kCountBytes, s));
         HIP_TRY(c, hipMemsetAsync(overflow, 0, sizeof(uint32_t), s));
         c->ev_valid = false;
         HIP_TRY(c, hipEventRecord(c->ev_start, s));
@@ -350,12 +374,12 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
             const uint64_t bits_w = std::min<uint64_t>(static_cast<uint64_t>(segs) * pl.seg_bits, pl.nbits - word0 * 32);
             const uint64_t fo = first_odd + 64 * word0;
             HIP_TRY(c, hipMemsetAsync(bcount, 0, segs * sizeof(uint32_t), s));
-            HIP_TRY(c, hipMemsetAsync(queue, 0, sizeof(uint32_t), s));
+            HIP_TRY(c, hipMemsetAsync(slot, 0, kQueueBytes, s));
             HIP_TRY(c, sv::launch_bucket_fill(c->d_primes + kPresievePrimes + n_small,
                                               c->d_inv + kPresievePrimes + n_small, n_large, fo, seg_log2, segs,
                                               buckets, bcount, static_cast<uint32_t>(depth), overflow, s));
             sv::RangeArgs ra{fo, bits_w, (bits_w + 31) / 32, d_words ? d_words + word0 : nullptr,
-                             pi_out ? slot : nullptr, queue, buckets, bcount, static_cast<uint32_t>(depth)};
+                             slot, pi_out != nullptr, buckets, bcount, static_cast<uint32_t>(depth)};
             sv::PrimeArgs pa{c->d_primes + kPresievePrimes, c->d_inv + kPresievePrimes, std::min(n_dense, n_small),
                              n_small};
             sieve_plan_info wp = pl;
@@ -365,16 +389,16 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
         }
         HIP_TRY(c, hipEventRecord(c->ev_stop, s));
         c->ev_valid = true;
-        uint32_t *h_flag = reinterpret_cast<uint32_t *>(c->h_count + 1);
+        uint32_t *h_flag = c->h_ctr + kQueues * kLineWords;
         if (pi_out)
-            HIP_TRY(c, hipMemcpyAsync(c->h_count, slot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, fetch_counts(c, slot, s));
         HIP_TRY(c, hipMemcpyAsync(h_flag, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
         c->slot_used[si] = true;
         HIP_TRY(c, hipStreamSynchronize(s));
         if (*h_flag == 0) {
             if (pi_out)
-                *pi_out = *c->h_count;  // odd primes only
+                *pi_out = mirrored_count(c);  // odd primes only
             return SIEVE_OK;
         }
         if (depth >= (1ull << 26))
@@ -412,14 +436,14 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
             *pi_out = pi + two;
         return SIEVE_OK;
     }
-    unsigned long long *slot = nullptr;
+    uint32_t *slot = nullptr;
     const int si = take_slot(c, &slot);
     if (si < 0)
         return si;
-    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, pi_out ? slot : nullptr,
-                     reinterpret_cast<uint32_t *>(slot + 1), nullptr, nullptr, 0};
+    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, pi_out != nullptr,
+                     nullptr, nullptr, 0};
     sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
-    HIP_TRY(c, hipMemsetAsync(slot, 0, 2 * sizeof(unsigned long long), s));
+    HIP_TRY(c, hipMemsetAsync(slot, 0, kCounterWords * sizeof(uint32_t), s));
     c->ev_valid = false;
     HIP_TRY(c, hipEventRecord(c->ev_start, s));
     HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
@@ -428,12 +452,12 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
     HIP_TRY(c, hipEventRecord(c->ev_stop, s));
     c->ev_valid = true;
     if (pi_out)
-        HIP_TRY(c, hipMemcpyAsync(c->h_count, slot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, fetch_counts(c, slot, s));
     HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
     c->slot_used[si] = true;
     if (pi_out) {
         HIP_TRY(c, hipStreamSynchronize(s));
-        *pi_out = *c->h_count + two;
+        *pi_out = mirrored_count(c) + two;
     }
     return SIEVE_OK;
 }
@@ -498,6 +522,7 @@ int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
     hipError_t e = sv::launch_batch(static_cast<sv::BatchHeader *>(const_cast<void *>(k.blob)),
                                     k.max_intervals, static_cast<const uint32_t *>(k.primes),
                                     static_cast<const double *>(k.inv), k.words,
+                                    static_cast<uint32_t *>(const_cast<void *>(k.item_counts)),
                                     static_cast<unsigned long long *>(const_cast<void *>(k.counts)),
                                     k.seg_words, k.threads, k.blocks, cs);
     if (e == hipSuccess)
@@ -534,7 +559,7 @@ namespace {
 uint64_t blob_items_offset(uint32_t n)
 {
     const uint64_t iv_bytes = static_cast<uint64_t>(n) * sizeof(sv::BatchInterval);
-    return kBlobAlign + (iv_bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
+    return kBlobIntervalOff + (iv_bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
 }
 uint64_t blob_bytes(uint32_t n, uint64_t items)
 {
@@ -551,6 +576,8 @@ int engine_reserve(sieve_ctx *c, BatchEngine &e, uint32_t n, uint64_t items)
         return st;
     if (int st = grow(c, e.counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long)))
         return st;
+    if (int st = grow(c, e.item_counts, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
+        return st;
     return grow_host(c, e.s_counts, e.counts.bytes);
 }
 
@@ -559,7 +586,7 @@ void engine_free(BatchEngine &e)
     if (e.done && e.pending)
         (void)hipEventSynchronize(e.done);
     drop_graph(e);
-    for (DevBuf *b : {&e.blob, &e.counts})
+    for (DevBuf *b : {&e.blob, &e.counts, &e.item_counts})
         if (b->p)
             (void)hipFree(b->p);
     for (HostBuf *b : {&e.s_blob, &e.s_counts})
@@ -579,7 +606,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
     const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
                                           sv::kFirstMarkedPrime);
-    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : (sw >= 2048 ? 512u : 256u);
+    const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : default_threads(sw);
     std::vector<std::pair<uint64_t, uint64_t>> spans;
     uint64_t max_bound = 0, items = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -606,8 +633,8 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
             return SIEVE_EINVAL;
     if (items > 0xffffffffull)
         return SIEVE_ERANGE;
-    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + items * sizeof(uint32_t) +
-                               n * sizeof(unsigned long long) + sizeof(sv::BatchHeader);
+    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + 2 * items * sizeof(uint32_t) +
+                               n * sizeof(unsigned long long) + kBlobIntervalOff;
     if (dev_bytes > c->hbm_budget)
         return SIEVE_ENOMEM;
 
@@ -625,7 +652,8 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
 
     // Intervals whose segments carry the most base primes go first, so the
     // cheapest work items are the ones left at the end of the queue.
-    sv::BatchInterval *h_iv = reinterpret_cast<sv::BatchInterval *>(blob + kBlobAlign);
+    std::memset(blob, 0, kBlobIntervalOff);  // header and work queues
+    sv::BatchInterval *h_iv = reinterpret_cast<sv::BatchInterval *>(blob + kBlobIntervalOff);
     uint32_t *h_item = reinterpret_cast<uint32_t *>(blob + blob_items_offset(n));
     e.order.resize(n);
     e.nmark.resize(n);
@@ -659,9 +687,9 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     sv::BatchHeader *h_hdr = reinterpret_cast<sv::BatchHeader *>(blob);
     h_hdr->n_intervals = n;
     h_hdr->n_items = static_cast<uint32_t>(items);
-    h_hdr->queue = 0;
+    h_hdr->seg_words = sw;
     h_hdr->pad = 0;
-    h_hdr->iv_off = kBlobAlign;
+    h_hdr->iv_off = kBlobIntervalOff;
     h_hdr->item_off = blob_items_offset(n);
     e.blob_used = bytes;
     e.n = n;
@@ -683,6 +711,7 @@ int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s
     GraphKey k{};
     k.blob = e.blob.p;
     k.counts = e.counts.p;
+    k.item_counts = e.item_counts.p;
     k.h_counts = e.s_counts.p;
     k.primes = c->d_primes + sv::kPresievePrimes;
     k.inv = c->d_inv + sv::kPresievePrimes;
@@ -770,11 +799,12 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipMalloc(&c->d_count, 2 * sieve_ctx::kSlots * sizeof(unsigned long long));
+        e = hipMalloc(&c->d_ctr, sieve_ctx::kSlots * sv::kCounterWords * sizeof(uint32_t));
     for (int i = 0; i < sieve_ctx::kSlots && e == hipSuccess; ++i)
         e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
     if (e == hipSuccess)
-        e = hipHostMalloc(&c->h_count, 2 * sizeof(unsigned long long), hipHostMallocDefault);
+        e = hipHostMalloc(&c->h_ctr, (sv::kQueues * sv::kLineWords + 64) * sizeof(uint32_t),
+                          hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess)
@@ -810,13 +840,13 @@ int sieve_destroy(sieve_ctx *c)
         (void)hipFree(c->d_primes);
     if (c->d_inv)
         (void)hipFree(c->d_inv);
-    if (c->d_count)
-        (void)hipFree(c->d_count);
+    if (c->d_ctr)
+        (void)hipFree(c->d_ctr);
     for (int i = 0; i < sieve_ctx::kSlots; ++i)
         if (c->slot_done[i])
             (void)hipEventDestroy(c->slot_done[i]);
-    if (c->h_count)
-        (void)hipHostFree(c->h_count);
+    if (c->h_ctr)
+        (void)hipHostFree(c->h_ctr);
     if (c->ev_start)
         (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop)
@@ -970,12 +1000,12 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             c->tuning = *best;
         return SIEVE_OK;
     }
-    // Segment sizes with the workgroup size that gives 16 waves per CU for
-    // that LDS footprint, times three dense/sparse bounds.
+    // Segment sizes with the workgroup size measured best for each on the
+    // count of [2, 10^10), times three dense/sparse bounds.
     struct SegChoice {
         uint32_t seg_bits, threads;
     };
-    const SegChoice segs[] = {{1u << 17, 256}, {1u << 18, 256}, {1u << 19, 512}, {1u << 20, 1024}};
+    const SegChoice segs[] = {{1u << 17, 512}, {1u << 18, 512}, {1u << 19, 1024}, {1u << 20, 1024}};
     const uint32_t dense_div[] = {1024, 512, 256};
     const sieve_tuning saved = c->tuning;
     std::vector<sieve_interval> count_only(iv, iv + n);

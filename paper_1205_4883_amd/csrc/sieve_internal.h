@@ -19,14 +19,29 @@ constexpr uint32_t kTableWords = 736;
 constexpr uint32_t kBootstrapLimit = 65536;
 constexpr uint32_t kBootstrapOddPrimes = 6541;  // odd primes below 2^16
 
+// Work counters and partial counts of one launch.  Device-scope atomics on
+// one address serialise across the chip (measured at about 12 ns apiece on
+// MI355X, enough to bound a whole launch when every wave adds its count per
+// segment), so a launch spreads them over kQueues work counters and kQueues
+// partial counts, each alone in a 256-byte line:
+//   queue q (uint32_t) at word q * kLineWords,
+//   count q (uint64_t) at word (kQueues + q) * kLineWords.
+// Work queue q hands out the items k * kQueues + q, k = 0, 1, ...; workgroup
+// b starts on queue b mod kQueues and moves on to the next queue when its own
+// runs dry, so every item is taken exactly once whatever the grid size, and
+// each workgroup makes at most kQueues failed pops before it leaves.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kLineWords = 64;
+constexpr uint32_t kCounterWords = 2 * kQueues * kLineWords;
+
 // One range as the segment kernels see it.
 struct RangeArgs {
     uint64_t first_odd;  // the odd integer of bit 0: (lo & ~1) + 1
     uint64_t nbits;      // odd integers in the range
     uint64_t n_words;    // ceil(nbits / 32)
     uint32_t *out;       // bitmap words of the range (word 0 = bit 0), or null
-    unsigned long long *count;  // += number of 1 bits (primes), or null
-    uint32_t *queue;     // segment counter, zero at launch
+    uint32_t *counters;  // kCounterWords words; the queues are zero at launch
+    bool count;          // add the number of 1 bits (primes) to the counts
     // Large-prime hit buckets of this launch's segments, or null: segment s
     // owns buckets[s * bucket_depth ..) with min(bucket_count[s], depth)
     // entries, each a bit offset inside the segment.
@@ -55,18 +70,23 @@ struct BatchInterval {
     uint32_t pad;
 };
 
-// Sizes and work counter of a batch launch, in device memory.  The header
+// Sizes of a batch launch, in device memory.  The header
 // starts one upload blob: the interval table sits at byte iv_off and the work
 // list (interval index of each item) at item_off, so one copy moves a batch.
+// The blob's second part, kCounterWords words at byte kBlobAlign, holds the
+// batch's work queues (zeroed by the reset kernel; the count lines are
+// unused).
 struct BatchHeader {
     uint32_t n_intervals;
     uint32_t n_items;
-    uint32_t queue;  // next item; zeroed by the reset kernel
+    uint32_t seg_words;  // words per work item (segment)
     uint32_t pad;
     uint64_t iv_off;
     uint64_t item_off;
 };
 constexpr uint64_t kBlobAlign = 256;
+constexpr uint64_t kBlobCounterOff = kBlobAlign;
+constexpr uint64_t kBlobIntervalOff = kBlobCounterOff + kCounterWords * 4;
 
 // Launchers (sieve_kernels.hip).  All return the first HIP error.
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
@@ -95,12 +115,14 @@ uint64_t compact_tmp_words(uint64_t n_words);
 hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t first_odd,
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
 
-// Reset kernel (counts[0 .. n_intervals) and the queue) followed by the
-// persistent batch kernel; both read their sizes and the table offsets from
-// the blob's header.  max_intervals sizes the reset grid.
+// Reset kernel (the work queues), the persistent batch kernel (each work
+// item's count into item_counts[item]) and the reduction kernel (counts[k] =
+// the sum over interval k's items); all three read their sizes and the table
+// offsets from the blob's header.  max_intervals sizes the reduction grid.
 hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
-                        const double *d_inv, uint32_t *d_words, unsigned long long *d_counts,
-                        uint32_t seg_words, uint32_t block_threads, uint32_t n_blocks, hipStream_t s);
+                        const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
+                        unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
+                        uint32_t n_blocks, hipStream_t s);
 
 // The segment kernels are built for a few static LDS sizes: the smallest
 // capacity (in words) that holds seg_words (0 if none), the LDS bytes a

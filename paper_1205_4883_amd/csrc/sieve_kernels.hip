@@ -246,15 +246,61 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// Sieve segment `seg` of one range into LDS and emit its words and count.
-// tabs: the pre-sieve tables in LDS; seg_lds: seg_words_max words of LDS.
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr uint32_t kNoItem = 0xffffffffu;
+
+// Thread 0's pop from a launch's spread work queues: the next item below
+// n_items, or kNoItem once every queue is dry.  q is the workgroup's current
+// queue and dry the number of queues it has found empty (a queue never
+// refills, so dry only grows and the workgroup leaves after kQueues failed
+// pops).
+__device__ __forceinline__ uint32_t pop_item(uint32_t *counters, uint32_t &q, uint32_t &dry, uint32_t n_items)
+{
+    while (dry < kQueues) {
+        const uint32_t k = atomicAdd(counters + q * kLineWords, 1u);
+        const uint64_t item = static_cast<uint64_t>(k) * kQueues + q;
+        if (item < n_items)
+            return static_cast<uint32_t>(item);
+        ++dry;
+        q = q + 1 == kQueues ? 0 : q + 1;
+    }
+    return kNoItem;
+}
+
+// Sum of every thread's v, added once per workgroup to *dst (red: one LDS
+// word per wavefront).
+__device__ __forceinline__ void block_add(unsigned long long v, unsigned long long *dst,
+                                          unsigned long long *red)
+{
+    v = wave_sum64(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long total = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w)
+            total += red[w];
+        if (total)
+            atomicAdd(dst, total);
+    }
+}
+
+// Sieve segment `seg` of one range into LDS and emit its words; returns the
+// number of primes among this thread's words.  tabs: the pre-sieve tables in
+// LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
+// its next __syncthreads.
 template <bool kWrite>
-__device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
-                              uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
-                              const uint32_t *primes, const double *inv, uint32_t n_dense,
-                              uint32_t n_primes, uint32_t *out, unsigned long long *count,
-                              const uint32_t *buckets = nullptr, const uint32_t *bucket_count = nullptr,
-                              uint32_t bucket_depth = 0)
+__device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
+                                  uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
+                                  const uint32_t *primes, const double *inv, uint32_t n_dense,
+                                  uint32_t n_primes, uint32_t *out, const uint32_t *buckets = nullptr,
+                                  const uint32_t *bucket_count = nullptr, uint32_t bucket_depth = 0)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
@@ -349,17 +395,15 @@ __device__ void sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t 
         if (kWrite)
             o[w] = v;
     }
-    c = wave_sum(c);
-    if ((t & 63) == 0 && count)
-        atomicAdd(count, static_cast<unsigned long long>(c));
-    __syncthreads();  // the LDS segment is reused by the next segment
+    return c;
 }
 
-// Resident workgroups pop segment numbers from a device counter (r.queue,
-// zero at launch) until every segment is taken, so the grid size need not
-// match the number of workgroups that fit on the device.  The LDS segment is a
-// static array of kSegMax words, so LDS addresses are compile-time offsets; a
-// launch may use any seg_words <= kSegMax.
+// Resident workgroups pop segment numbers from the launch's work queues
+// (zero at launch) until every segment is taken, so the grid size need not
+// match the number of workgroups that fit on the device; each workgroup adds
+// its share of the count once, as it leaves.  The LDS segment is a static
+// array of kSegMax words, so LDS addresses are compile-time offsets; a launch
+// may use any seg_words <= kSegMax.
 // (Registers are capped so that eight waves fit per SIMD where LDS allows.)
 template <uint32_t kSegMax, bool kWrite>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) range_kernel(RangeArgs r, PrimeArgs pa, uint32_t seg_words,
@@ -367,71 +411,116 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 {
     __shared__ uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t seg_sh;
+    __shared__ unsigned long long red[16];
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
+    uint32_t q = blockIdx.x % kQueues, dry = 0;
+    unsigned long long acc = 0;
     for (;;) {
-        __syncthreads();
+        __syncthreads();  // tables built / the previous segment's LDS is free
         if (threadIdx.x == 0)
-            seg_sh = atomicAdd(r.queue, 1u);
+            seg_sh = pop_item(r.counters, q, dry, n_segments);
         __syncthreads();
         const uint32_t s = seg_sh;
-        if (s >= n_segments)
+        if (s == kNoItem)
             break;
-        sieve_segment<kWrite>(tabs, seg, seg_words, s, r.first_odd, r.nbits, r.n_words, pa.primes,
-                              pa.inv, pa.n_dense, pa.n_primes, r.out, r.count, r.buckets, r.bucket_count,
-                              r.bucket_depth);
+        acc += sieve_segment<kWrite>(tabs, seg, seg_words, s, r.first_odd, r.nbits, r.n_words, pa.primes,
+                                     pa.inv, pa.n_dense, pa.n_primes, r.out, r.buckets, r.bucket_count,
+                                     r.bucket_depth);
     }
+    if (r.count)
+        block_add(acc,
+                  reinterpret_cast<unsigned long long *>(r.counters + (kQueues + blockIdx.x % kQueues) * kLineWords),
+                  red);
 }
 
 // Persistent batch kernel: workgroups pop (interval, segment) items from the
-// header's counter until the queue is empty (hdr->n_items items).  Every
-// workgroup leaves the loop once the counter passes n_items, so the grid
-// always drains.  All sizes are read from device memory, so one captured
+// blob's work queues until every item is taken (hdr->n_items items).  Every
+// workgroup leaves once all queues are dry, so the grid always drains.  Each
+// item's count goes to item_counts[item] with a plain store (thread 0, at
+// the next pop).  All sizes are read from device memory, so one captured
 // graph serves batches of any size up to its buffers' capacity.
 template <uint32_t kSegMax>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(
     BatchHeader *hdr, const uint32_t *primes, const double *inv, uint32_t *words,
-    unsigned long long *counts, uint32_t seg_words)
+    uint32_t *item_counts, uint32_t seg_words)
 {
     __shared__ uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
+    __shared__ uint32_t red[16];
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
     const uint32_t n_items = hdr->n_items;
-    const char *blob = reinterpret_cast<const char *>(hdr);
+    char *blob = reinterpret_cast<char *>(hdr);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(blob + kBlobCounterOff);
     const BatchInterval *ivs = reinterpret_cast<const BatchInterval *>(blob + hdr->iv_off);
     const uint32_t *item_iv = reinterpret_cast<const uint32_t *>(blob + hdr->item_off);
+    uint32_t q = blockIdx.x % kQueues, dry = 0;
+    uint32_t prev = kNoItem;
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0)
-            item_sh = atomicAdd(&hdr->queue, 1u);
+        __syncthreads();  // red[] holds the previous item's wave counts; LDS is free
+        if (threadIdx.x == 0) {
+            if (prev != kNoItem) {
+                uint32_t total = 0;
+                for (uint32_t w = 0; w < (blockDim.x >> 6); ++w)
+                    total += red[w];
+                item_counts[prev] = total;
+            }
+            item_sh = pop_item(counters, q, dry, n_items);
+        }
         __syncthreads();
         const uint32_t item = item_sh;
-        if (item >= n_items)
+        if (item == kNoItem)
             break;
         const uint32_t k = item_iv[item];
         const BatchInterval iv = ivs[k];
         const uint64_t s = item - iv.seg_begin;
+        uint32_t c;
         if (iv.word_offset != ~0ull)
-            sieve_segment<true>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes,
-                                inv, iv.n_dense, iv.n_primes, words + iv.word_offset, counts + k);
+            c = sieve_segment<true>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
+                                    iv.n_dense, iv.n_primes, words + iv.word_offset);
         else
-            sieve_segment<false>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes,
-                                 inv, iv.n_dense, iv.n_primes, nullptr, counts + k);
+            c = sieve_segment<false>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
+                                     iv.n_dense, iv.n_primes, nullptr);
+        c = wave_sum(c);
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = c;
+        prev = item;
     }
 }
 
-// Zero the per-interval counts and the work counter of a batch (a kernel, not
-// a memset, so that it can sit in a captured graph).
-__global__ void __launch_bounds__(256) batch_reset_kernel(BatchHeader *hdr, unsigned long long *counts)
+// Zero a batch's work queues (a kernel, not a memset, so that it can sit in a
+// captured graph).
+__global__ void __launch_bounds__(64) batch_reset_kernel(BatchHeader *hdr)
+{
+    uint32_t *counters = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hdr) + kBlobCounterOff);
+    if (threadIdx.x < kQueues)
+        counters[threadIdx.x * kLineWords] = 0;
+}
+
+// counts[k] = the sum of item_counts over interval k's items, one wavefront
+// per interval.
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchHeader *hdr, const uint32_t *item_counts,
+                                                           unsigned long long *counts)
 {
     const uint32_t n = hdr->n_intervals;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        counts[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        hdr->queue = 0;
+    const uint32_t sw = hdr->seg_words;
+    const BatchInterval *ivs =
+        reinterpret_cast<const BatchInterval *>(reinterpret_cast<const char *>(hdr) + hdr->iv_off);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; k < n; k += waves) {
+        const BatchInterval iv = ivs[k];
+        const uint64_t segs = (iv.n_words + sw - 1) / sw;
+        unsigned long long c = 0;
+        for (uint64_t j = lane; j < segs; j += 64)
+            c += item_counts[iv.seg_begin + j];
+        c = wave_sum64(c);
+        if (lane == 0)
+            counts[k] = c;
+    }
 }
 
 // Odd integers below 2^16 in one workgroup: bit i of bits[] is 2i + 1,
@@ -715,11 +804,11 @@ void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words
 
 template <uint32_t kSegMax>
 void launch_batch_cap(BatchHeader *d_blob, const uint32_t *d_primes, const double *d_inv,
-                      uint32_t *d_words, unsigned long long *d_counts, uint32_t seg_words,
-                      uint32_t threads, uint32_t grid, hipStream_t s)
+                      uint32_t *d_words, uint32_t *d_item_counts, uint32_t seg_words, uint32_t threads,
+                      uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_blob, d_primes, d_inv,
-                       d_words, d_counts, seg_words);
+                       d_words, d_item_counts, seg_words);
 }
 }  // namespace
 
@@ -795,22 +884,24 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
 }
 
 hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
-                        const double *d_inv, uint32_t *d_words, unsigned long long *d_counts,
-                        uint32_t seg_words, uint32_t block_threads, uint32_t n_blocks, hipStream_t s)
+                        const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
+                        unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
+                        uint32_t n_blocks, hipStream_t s)
 {
     if (n_blocks == 0)
         return hipSuccess;
-    const uint32_t reset_blocks = (max_intervals + 255) / 256 > 0 ? (max_intervals + 255) / 256 : 1;
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(reset_blocks < 1024 ? reset_blocks : 1024), dim3(256), 0, s,
-                       d_blob, d_counts);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, d_blob);
     switch (seg_capacity_for(seg_words)) {
-    case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
-    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_counts, seg_words, block_threads, n_blocks, s); break;
+    case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
+    case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
+    case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
+    case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
+    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
     default: return hipErrorInvalidValue;
     }
+    const uint32_t waves_blocks = (max_intervals + 3) / 4;  // four wavefronts per block
+    const uint32_t rb = waves_blocks == 0 ? 1 : (waves_blocks < 1024 ? waves_blocks : 1024);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(rb), dim3(256), 0, s, d_blob, d_item_counts, d_counts);
     return hipGetLastError();
 }
 

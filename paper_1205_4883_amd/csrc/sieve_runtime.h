@@ -31,23 +31,25 @@ struct HostBuf {  // pinned host memory
 
 // Everything a captured batch graph bakes in.
 struct GraphKey {
-    const void *blob, *counts, *h_counts, *primes, *inv;
+    const void *blob, *counts, *item_counts, *h_counts, *primes, *inv;
     uint32_t *words;
     uint32_t seg_words, threads, blocks, max_intervals;
     size_t counts_bytes;
     bool operator==(const GraphKey &o) const
     {
-        return blob == o.blob && counts == o.counts && h_counts == o.h_counts && primes == o.primes &&
-               inv == o.inv && words == o.words && seg_words == o.seg_words && threads == o.threads &&
-               blocks == o.blocks && max_intervals == o.max_intervals && counts_bytes == o.counts_bytes;
+        return blob == o.blob && counts == o.counts && item_counts == o.item_counts && h_counts == o.h_counts &&
+               primes == o.primes && inv == o.inv && words == o.words && seg_words == o.seg_words &&
+               threads == o.threads && blocks == o.blocks && max_intervals == o.max_intervals &&
+               counts_bytes == o.counts_bytes;
     }
 };
 
 // One batch in flight: the interval table and work list (pinned staging and
-// device copies), per-interval counts, the batch header and the captured
-// graph that launches it.  A context owns one; the server owns one per lane.
+// device copies), per-item and per-interval counts, the batch header and the
+// captured graph that launches it.  A context owns one; the server owns one
+// per lane.
 struct BatchEngine {
-    DevBuf blob, counts;  // blob: header, interval table, work list
+    DevBuf blob, counts, item_counts;  // blob: header, work queues, interval table, work list
     HostBuf s_blob, s_counts;
     uint64_t blob_used = 0;  // bytes of the staged blob
     std::vector<uint32_t> order, nmark, ndense;
@@ -80,15 +82,18 @@ struct sieve_ctx {
     uint32_t *d_primes = nullptr;
     double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
 
-    // Per-call device words {count, segment queue}: kSlots slots used in
-    // turn, each guarded by an event so that an asynchronous call still
-    // running on another stream never sees its slot reset.
+    // Per-call device counters (work queues and partial counts, kCounterWords
+    // words each): kSlots slots used in turn, each guarded by an event so
+    // that an asynchronous call still running on another stream never sees
+    // its slot reset.
     static constexpr int kSlots = 16;
-    unsigned long long *d_count = nullptr;  // 2 * kSlots words
+    uint32_t *d_ctr = nullptr;  // kSlots * kCounterWords words
     hipEvent_t slot_done[kSlots] = {};
     bool slot_used[kSlots] = {};
     int next_slot = 0;
-    unsigned long long *h_count = nullptr;  // pinned
+    // pinned: the count lines of a slot (kQueues * kLineWords words), then
+    // one spare word (the bucket overflow flag)
+    uint32_t *h_ctr = nullptr;
 
     // events bracketing the last sieve kernel launch (range or batch)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;

@@ -69,6 +69,14 @@ def test_plan_tuning_resolution():
     assert p["seg_bits"] == 65536 and p["dense_limit"] == 500 and p["block_threads"] == 512
     p = sv.sieve_plan(2, 10**10, tuning=dict(dense_limit=3))
     assert p["dense_limit"] == 37
+    # defaults: the largest LDS segment (2^19 bits) for long ranges, with
+    # 1024 threads; smaller segments take fewer threads
+    p = sv.sieve_plan(2, 10**10)
+    assert p["seg_bits"] == 1 << 19 and p["block_threads"] == 1024 and p["dense_limit"] == 1024
+    p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 18))
+    assert p["block_threads"] == 512
+    p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 15))
+    assert p["block_threads"] == 256
 
 
 @pytest.mark.parametrize("lo,hi,tuning,status", [
