@@ -91,7 +91,11 @@ constexpr uint64_t kBlobIntervalOff = kBlobCounterOff + kCounterWords * 4;
 // Launchers (sieve_kernels.hip).  All return the first HIP error.
 hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream_t s);
 
-// Grid: min(n_segments, max_blocks) workgroups draining the segment queue.
+// Grid: min(n_segments, max_blocks) workgroups draining the work queues.
+// The work items are runs of consecutive segments (range_chunks: n_chunks
+// runs of `chunk` segments, then the remaining segments one by one).
+constexpr uint32_t kMaxChunk = 8;
+void range_chunks(uint32_t n_segments, uint32_t grid, uint32_t *chunk, uint32_t *n_chunks);
 hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_segments, uint32_t max_blocks,
                         hipStream_t s);

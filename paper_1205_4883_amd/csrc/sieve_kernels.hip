@@ -184,20 +184,30 @@ __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t 
         lds_or(ptr, mask);
 }
 
-// Sparse marking of one prime by one lane: the multiples p*m with m prime to
-// 15, from the segment's first odd multiple (bit offset o, m mod 30 = m30).
-// The eight offsets of one turn of the wheel (15 odd steps, 15p bits) are
-// computed once, so a mark inside a full turn costs one add plus the
-// address and mask; the last partial turn is guarded mark by mark.
-__device__ __forceinline__ void mark_sparse(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
-                                            uint32_t m30)
+// Step from the odd multiple at bit offset o (multiplier m, m mod 30 = m30)
+// to the first one whose multiplier is prime to 15 (at most two odd steps);
+// returns the multiplier's position in the cycle of the eight wheel
+// residues.
+__device__ __forceinline__ uint32_t wheel_start(uint32_t p, uint32_t &o, uint32_t m30)
 {
-    // step to the first m prime to 15 (at most two odd steps)
     while (((kWheelMask >> m30) & 1u) == 0) {
         m30 += 2;
         o += p;
     }
-    const uint32_t idx = __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;  // position in the cycle
+    return __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;
+}
+
+// Sparse marking of one prime by one lane: the multiples p*m with m prime to
+// 15 from bit offset o (whose multiplier sits at wheel position idx) up to
+// lim_bits.  The eight offsets of one turn of the wheel (15 odd steps, 15p
+// bits) are computed once, so a mark inside a full turn costs one add plus
+// the address and mask; the last partial turn is guarded mark by mark.
+// Returns the offset of the first multiple left unmarked (at or past
+// lim_bits) and sets idx to its wheel position, so that the next segment
+// can continue from there.
+__device__ __forceinline__ uint32_t mark_wheel(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
+                                               uint32_t &idx)
+{
     const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
     uint32_t d[8];
     d[0] = 0;
@@ -213,13 +223,19 @@ __device__ __forceinline__ void mark_sparse(uint32_t *seg, uint32_t lim_bits, ui
             lds_or(seg + (x >> 5), 1u << (x & 31));
         }
     }
+    uint32_t next = base + d[7], step = 7;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         const uint32_t x = base + d[j];
-        if (x >= lim_bits)
+        if (x >= lim_bits) {
+            next = x;
+            step = j;
             break;
+        }
         lds_or(seg + (x >> 5), 1u << (x & 31));
     }
+    idx = (idx + step) & 7u;
+    return next;
 }
 
 // The first word of a range: 1 is not prime; 3..31 are primes that the
@@ -291,105 +307,128 @@ __device__ __forceinline__ void block_add(unsigned long long v, unsigned long lo
     }
 }
 
-// Sieve segment `seg` of one range into LDS and emit its words; returns the
-// number of primes among this thread's words.  tabs: the pre-sieve tables in
-// LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
-// its next __syncthreads.
-template <bool kWrite>
-__device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
-                                  uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
-                                  const uint32_t *primes, const double *inv, uint32_t n_dense,
-                                  uint32_t n_primes, uint32_t *out, const uint32_t *buckets = nullptr,
-                                  const uint32_t *bucket_count = nullptr, uint32_t bucket_depth = 0)
+// Where one segment of a range lies.
+struct SegGeom {
+    uint64_t w0;        // first word of the segment in the range
+    uint64_t n0;        // odd integer of the segment's bit 0
+    double nf;          // n0 as a double (exact: n0 < 2^53)
+    uint32_t sw;        // words in the segment (the last one may be short)
+    uint32_t lim_bits;  // sw * 32
+};
+
+__device__ __forceinline__ SegGeom seg_geom(uint64_t seg, uint32_t seg_words_max, uint64_t first_odd,
+                                            uint64_t n_words)
+{
+    SegGeom g;
+    g.w0 = seg * seg_words_max;
+    const uint64_t left = n_words - g.w0;
+    g.sw = left < seg_words_max ? static_cast<uint32_t>(left) : seg_words_max;
+    g.lim_bits = g.sw * 32;
+    g.n0 = first_odd + 64 * g.w0;
+    g.nf = static_cast<double>(g.n0);
+    return g;
+}
+
+// 1. pre-sieve.  Bit i of the segment is the odd integer 2x + 1 with
+//    x = (n0 >> 1) + i; pattern phases are x mod L.
+__device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg_lds, const SegGeom &g)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
-    const uint64_t w0 = seg * seg_words_max;  // first word of the segment in the range
-    const uint64_t left = n_words - w0;
-    const uint32_t sw = left < seg_words_max ? static_cast<uint32_t>(left) : seg_words_max;
-    const uint32_t lim_bits = sw * 32;
-    const uint64_t n0 = first_odd + 64 * w0;  // odd integer of the segment's bit 0
-    const double nf = static_cast<double>(n0);
-
-    // 1. pre-sieve.  Bit g of the segment is the odd integer 2x + 1 with
-    //    x = (n0 >> 1) + g; pattern phases are x mod L.
-    {
-        const uint64_t x0 = (n0 >> 1) + 32ull * t;
-        uint32_t ja = static_cast<uint32_t>(x0 % kLA);
-        uint32_t jb = static_cast<uint32_t>(x0 % kLB);
-        uint32_t jc = static_cast<uint32_t>(x0 % kLC);
-        const uint32_t sa = (32u * nthreads) % kLA;
-        const uint32_t sb = (32u * nthreads) % kLB;
-        const uint32_t sc = (32u * nthreads) % kLC;
-        const uint32_t *ta = tabs;
-        const uint32_t *tb = tabs + kWA;
-        const uint32_t *tc = tabs + kWA + kWB;
-        for (uint32_t w = t; w < sw; w += nthreads) {
-            seg_lds[w] = pattern_at(ta, ja) | pattern_at(tb, jb) | pattern_at(tc, jc);
-            ja += sa;
-            ja = min(ja, ja - kLA);  // unsigned: subtract L once if ja >= L
-            jb += sb;
-            jb = min(jb, jb - kLB);
-            jc += sc;
-            jc = min(jc, jc - kLC);
-        }
+    const uint64_t x0 = (g.n0 >> 1) + 32ull * t;
+    uint32_t ja = static_cast<uint32_t>(x0 % kLA);
+    uint32_t jb = static_cast<uint32_t>(x0 % kLB);
+    uint32_t jc = static_cast<uint32_t>(x0 % kLC);
+    const uint32_t sa = (32u * nthreads) % kLA;
+    const uint32_t sb = (32u * nthreads) % kLB;
+    const uint32_t sc = (32u * nthreads) % kLC;
+    const uint32_t *ta = tabs;
+    const uint32_t *tb = tabs + kWA;
+    const uint32_t *tc = tabs + kWA + kWB;
+    for (uint32_t w = t; w < g.sw; w += nthreads) {
+        seg_lds[w] = pattern_at(ta, ja) | pattern_at(tb, jb) | pattern_at(tc, jc);
+        ja += sa;
+        ja = min(ja, ja - kLA);  // unsigned: subtract L once if ja >= L
+        jb += sb;
+        jb = min(jb, jb - kLB);
+        jc += sc;
+        jc = min(jc, jc - kLC);
     }
-    __syncthreads();
+}
 
-    // 2a. dense primes: one wavefront per prime.  Lane l of wave w computes
-    //     the start of prime r*64*nw + l*nw + w, so each wave gets an
-    //     interleaved, evenly weighted share of the primes; the wave then
-    //     marks its (up to) 64 primes one after another.
-    {
-        const uint32_t lane = t & 63;
-        const uint32_t wave = t >> 6;
-        const uint32_t nw = nthreads >> 6;
-        for (uint32_t r0 = 0; r0 + wave < n_dense; r0 += 64 * nw) {
-            const uint32_t i = r0 + lane * nw + wave;
-            uint32_t p = 0, s0 = 0, m30 = 0;
-            if (i < n_dense) {
-                p = primes[i];
-                const Start st = first_multiple(n0, nf, p, inv[i], lim_bits);
-                s0 = st.off;
-                m30 = st.m30;
-            }
-            const uint32_t cnt = min(64u, (n_dense - r0 - wave + nw - 1) / nw);
-            for (uint32_t l = 0; l < cnt; ++l)
-                mark_dense(seg_lds, sw, __builtin_amdgcn_readlane(p, l),
-                           __builtin_amdgcn_readlane(s0, l), __builtin_amdgcn_readlane(m30, l), lane);
+// 2a. dense primes: one wavefront per prime.  Lane l of wave w computes the
+//     start of prime r*64*nw + l*nw + w, so each wave gets an interleaved,
+//     evenly weighted share of the primes; the wave then marks its (up to)
+//     64 primes one after another.
+__device__ __forceinline__ void seg_dense(uint32_t *seg_lds, const SegGeom &g, const uint32_t *primes,
+                                          const double *inv, uint32_t n_dense)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = t & 63;
+    const uint32_t wave = t >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    for (uint32_t r0 = 0; r0 + wave < n_dense; r0 += 64 * nw) {
+        const uint32_t i = r0 + lane * nw + wave;
+        uint32_t p = 0, s0 = 0, m30 = 0;
+        if (i < n_dense) {
+            p = primes[i];
+            const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
+            s0 = st.off;
+            m30 = st.m30;
         }
+        const uint32_t cnt = min(64u, (n_dense - r0 - wave + nw - 1) / nw);
+        for (uint32_t l = 0; l < cnt; ++l)
+            mark_dense(seg_lds, g.sw, __builtin_amdgcn_readlane(p, l), __builtin_amdgcn_readlane(s0, l),
+                       __builtin_amdgcn_readlane(m30, l), lane);
     }
-    // 2b. sparse primes: one lane per prime.
-    for (uint32_t i = n_dense + t; i < n_primes; i += nthreads) {
+}
+
+// 2b. sparse primes [i_begin, n_primes): one lane per prime, each start
+//     computed afresh for this segment.
+__device__ __forceinline__ void seg_sparse(uint32_t *seg_lds, const SegGeom &g, const uint32_t *primes,
+                                           const double *inv, uint32_t i_begin, uint32_t n_primes)
+{
+    for (uint32_t i = i_begin + threadIdx.x; i < n_primes; i += blockDim.x) {
         const uint32_t p = primes[i];
-        const Start st = first_multiple(n0, nf, p, inv[i], lim_bits);
-        mark_sparse(seg_lds, lim_bits, p, st.off, st.m30);
+        const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
+        uint32_t o = st.off;
+        uint32_t idx = wheel_start(p, o, st.m30);
+        (void)mark_wheel(seg_lds, g.lim_bits, p, o, idx);
     }
-    // 2c. large primes: the segment's bucket of precomputed hits.
-    if (buckets) {
-        const uint32_t nb = min(bucket_count[seg], bucket_depth);
-        const uint32_t *bk = buckets + seg * bucket_depth;
-        for (uint32_t e = t; e < nb; e += nthreads) {
-            const uint32_t b = bk[e];
-            lds_or(seg_lds + (b >> 5), 1u << (b & 31));
-        }
-    }
-    __syncthreads();
+}
 
-    // 3. count (and store) the unmarked bits.  Only the range's first word
-    //    (small primes, 1) and last word (tail bits) need fixing; both are
-    //    patched in LDS by one thread before the sweep.
+// 2c. large primes: the segment's bucket of precomputed hits.
+__device__ __forceinline__ void seg_buckets(uint32_t *seg_lds, uint64_t seg, const uint32_t *buckets,
+                                            const uint32_t *bucket_count, uint32_t bucket_depth)
+{
+    const uint32_t nb = min(bucket_count[seg], bucket_depth);
+    const uint32_t *bk = buckets + seg * bucket_depth;
+    for (uint32_t e = threadIdx.x; e < nb; e += blockDim.x) {
+        const uint32_t b = bk[e];
+        lds_or(seg_lds + (b >> 5), 1u << (b & 31));
+    }
+}
+
+// 3. count (and store) the unmarked bits; returns this thread's count.  The
+//    marking must be complete (a __syncthreads after it).  Only the range's
+//    first word (small primes, 1) and last word (tail bits) need fixing;
+//    both are patched in LDS by one thread before the sweep.
+template <bool kWrite>
+__device__ __forceinline__ uint32_t seg_count(uint32_t *seg_lds, const SegGeom &g, uint64_t first_odd,
+                                              uint64_t nbits, uint64_t n_words, uint32_t *out)
+{
+    const uint32_t t = threadIdx.x;
     if (t == 0) {
-        if (w0 == 0)
+        if (g.w0 == 0)
             seg_lds[0] = ~fix_first_word(~seg_lds[0], first_odd);
         const uint32_t tail = static_cast<uint32_t>(nbits & 31);
-        if (tail && w0 + sw == n_words)
-            seg_lds[sw - 1] |= ~((1u << tail) - 1);
+        if (tail && g.w0 + g.sw == n_words)
+            seg_lds[g.sw - 1] |= ~((1u << tail) - 1);
     }
     __syncthreads();
     uint32_t c = 0;
-    uint32_t *o = kWrite ? out + w0 : nullptr;
-    for (uint32_t w = t; w < sw; w += nthreads) {
+    uint32_t *o = kWrite ? out + g.w0 : nullptr;
+    for (uint32_t w = t; w < g.sw; w += blockDim.x) {
         const uint32_t v = ~seg_lds[w];
         c += __popc(v);
         if (kWrite)
@@ -398,36 +437,105 @@ __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint3
     return c;
 }
 
-// Resident workgroups pop segment numbers from the launch's work queues
-// (zero at launch) until every segment is taken, so the grid size need not
-// match the number of workgroups that fit on the device; each workgroup adds
-// its share of the count once, as it leaves.  The LDS segment is a static
-// array of kSegMax words, so LDS addresses are compile-time offsets; a launch
-// may use any seg_words <= kSegMax.
-// (Registers are capped so that eight waves fit per SIMD where LDS allows.)
+// Sieve segment `seg` of one range into LDS and emit its words; returns the
+// number of primes among this thread's words.  tabs: the pre-sieve tables in
+// LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
+// its next __syncthreads.
+template <bool kWrite>
+__device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
+                                  uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
+                                  const uint32_t *primes, const double *inv, uint32_t n_dense,
+                                  uint32_t n_primes, uint32_t *out)
+{
+    const SegGeom g = seg_geom(seg, seg_words_max, first_odd, n_words);
+    seg_presieve(tabs, seg_lds, g);
+    __syncthreads();
+    seg_dense(seg_lds, g, primes, inv, n_dense);
+    seg_sparse(seg_lds, g, primes, inv, n_dense, n_primes);
+    __syncthreads();
+    return seg_count<kWrite>(seg_lds, g, first_odd, nbits, n_words, out);
+}
+
+// Sparse primes whose next multiple a lane carries from one segment to the
+// next, per thread; a carried state packs the offset (below kCarryCap) with
+// the wheel position in the top three bits.
+constexpr int kCarry = 4;
+constexpr uint32_t kCarryCap = 1u << 28;
+constexpr uint32_t kCarryNone = 0xffffffffu;
+
+// Resident workgroups pop work items from the launch's work queues (zero at
+// launch) until every item is taken, so the grid size need not match the
+// number of workgroups that fit on the device.  Items [0, n_chunks) are runs
+// of `chunk` consecutive segments, the rest single segments (the tail, so
+// that workgroups finish together).  Inside a run each lane carries the next
+// multiple of its first kCarry sparse primes from segment to segment instead
+// of dividing again.  Each workgroup adds its share of the count once, as it
+// leaves.  The LDS segment is a static array of kSegMax words, so LDS
+// addresses are compile-time offsets; a launch may use any seg_words <=
+// kSegMax.  (Registers are capped so that eight waves fit per SIMD where LDS
+// allows.)
 template <uint32_t kSegMax, bool kWrite>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) range_kernel(RangeArgs r, PrimeArgs pa, uint32_t seg_words,
-                                                      uint32_t n_segments)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) range_kernel(
+    RangeArgs r, PrimeArgs pa, uint32_t seg_words, uint32_t n_segments, uint32_t chunk, uint32_t n_chunks)
 {
     __shared__ uint32_t lds[kTableWords + kSegMax];
-    __shared__ uint32_t seg_sh;
+    __shared__ uint32_t item_sh;
     __shared__ unsigned long long red[16];
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
     build_tables(tabs);
+    const uint32_t t = threadIdx.x;
+    const uint32_t n_items = n_chunks + (n_segments - n_chunks * chunk);
+    const uint32_t carry_end = min(pa.n_primes, pa.n_dense + kCarry * blockDim.x);
     uint32_t q = blockIdx.x % kQueues, dry = 0;
     unsigned long long acc = 0;
+    uint32_t carry[kCarry];
     for (;;) {
         __syncthreads();  // tables built / the previous segment's LDS is free
-        if (threadIdx.x == 0)
-            seg_sh = pop_item(r.counters, q, dry, n_segments);
+        if (t == 0)
+            item_sh = pop_item(r.counters, q, dry, n_items);
         __syncthreads();
-        const uint32_t s = seg_sh;
-        if (s == kNoItem)
+        const uint32_t item = item_sh;
+        if (item == kNoItem)
             break;
-        acc += sieve_segment<kWrite>(tabs, seg, seg_words, s, r.first_odd, r.nbits, r.n_words, pa.primes,
-                                     pa.inv, pa.n_dense, pa.n_primes, r.out, r.buckets, r.bucket_count,
-                                     r.bucket_depth);
+        const uint64_t first = item < n_chunks ? static_cast<uint64_t>(item) * chunk
+                                               : static_cast<uint64_t>(n_chunks) * chunk + (item - n_chunks);
+        const uint32_t count = item < n_chunks ? chunk : 1;
+        for (uint32_t k = 0; k < count; ++k) {
+            if (k)
+                __syncthreads();  // the previous segment's count has read the LDS
+            const SegGeom g = seg_geom(first + k, seg_words, r.first_odd, r.n_words);
+            seg_presieve(tabs, seg, g);
+            __syncthreads();
+            seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense);
+#pragma unroll
+            for (int j = 0; j < kCarry; ++j) {
+                const uint32_t i = pa.n_dense + t + j * blockDim.x;
+                if (i >= carry_end)
+                    break;
+                const uint32_t p = pa.primes[i];
+                uint32_t o, idx;
+                if (k == 0 || carry[j] == kCarryNone) {
+                    const Start st = first_multiple(g.n0, g.nf, p, pa.inv[i], kCarryCap);
+                    o = st.off;
+                    if (o >= kCarryCap) {  // p*p lies far ahead: look again next segment
+                        carry[j] = kCarryNone;
+                        continue;
+                    }
+                    idx = wheel_start(p, o, st.m30);
+                } else {
+                    o = carry[j] & (kCarryCap - 1);
+                    idx = carry[j] >> 29;
+                }
+                o = mark_wheel(seg, g.lim_bits, p, o, idx) - g.lim_bits;
+                carry[j] = o < kCarryCap ? (idx << 29) | o : kCarryNone;
+            }
+            seg_sparse(seg, g, pa.primes, pa.inv, carry_end, pa.n_primes);
+            if (r.buckets)
+                seg_buckets(seg, first + k, r.buckets, r.bucket_count, r.bucket_depth);
+            __syncthreads();
+            acc += seg_count<kWrite>(seg, g, r.first_odd, r.nbits, r.n_words, r.out);
+        }
     }
     if (r.count)
         block_add(acc,
@@ -674,12 +782,8 @@ template <typename F>
 __device__ __forceinline__ void walk_hits(uint64_t n0, uint32_t p, double inv, uint32_t chunk_bits, F hit)
 {
     const Start st = first_multiple(n0, static_cast<double>(n0), p, inv, chunk_bits);
-    uint32_t o = st.off, m30 = st.m30;
-    while (((kWheelMask >> m30) & 1u) == 0) {
-        m30 += 2;
-        o += p;
-    }
-    const uint32_t idx = __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;
+    uint32_t o = st.off;
+    const uint32_t idx = wheel_start(p, o, st.m30);
     uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
     while (o < chunk_bits) {
         hit(o);
@@ -792,14 +896,14 @@ hipError_t launch_reciprocals(const uint32_t *d_primes, uint32_t n, double *d_in
 namespace {
 template <uint32_t kSegMax>
 void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words, uint32_t threads,
-                      uint32_t n_segments, uint32_t grid, hipStream_t s)
+                      uint32_t n_segments, uint32_t chunk, uint32_t n_chunks, uint32_t grid, hipStream_t s)
 {
     if (r.out)
         hipLaunchKernelGGL((range_kernel<kSegMax, true>), dim3(grid), dim3(threads), 0, s, r, p, seg_words,
-                           n_segments);
+                           n_segments, chunk, n_chunks);
     else
         hipLaunchKernelGGL((range_kernel<kSegMax, false>), dim3(grid), dim3(threads), 0, s, r, p, seg_words,
-                           n_segments);
+                           n_segments, chunk, n_chunks);
 }
 
 template <uint32_t kSegMax>
@@ -847,18 +951,37 @@ uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
     }
 }
 
+void range_chunks(uint32_t n_segments, uint32_t grid, uint32_t *chunk, uint32_t *n_chunks)
+{
+    // the last 2 * grid segments go singly; the rest in runs that give each
+    // workgroup about three runs
+    const uint32_t tail = n_segments < 2 * grid ? n_segments : 2 * grid;
+    const uint32_t bulk = n_segments - tail;
+    uint32_t c = grid ? bulk / (3 * grid) : 0;
+    c = c < kMaxChunk ? c : kMaxChunk;
+    if (c < 2) {
+        *chunk = 1;
+        *n_chunks = 0;
+        return;
+    }
+    *chunk = c;
+    *n_chunks = bulk / c;
+}
+
 hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words,
                         uint32_t block_threads, uint32_t n_segments, uint32_t max_blocks, hipStream_t s)
 {
     const uint32_t grid = n_segments < max_blocks ? n_segments : max_blocks;
     if (grid == 0)
         return hipSuccess;
+    uint32_t chunk = 1, n_chunks = 0;
+    range_chunks(n_segments, grid, &chunk, &n_chunks);
     switch (seg_capacity_for(seg_words)) {
-    case 512: launch_range_cap<512>(r, p, seg_words, block_threads, n_segments, grid, s); break;
-    case 2048: launch_range_cap<2048>(r, p, seg_words, block_threads, n_segments, grid, s); break;
-    case 8192: launch_range_cap<8192>(r, p, seg_words, block_threads, n_segments, grid, s); break;
-    case 16384: launch_range_cap<16384>(r, p, seg_words, block_threads, n_segments, grid, s); break;
-    case 32768: launch_range_cap<32768>(r, p, seg_words, block_threads, n_segments, grid, s); break;
+    case 512: launch_range_cap<512>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
+    case 2048: launch_range_cap<2048>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
+    case 8192: launch_range_cap<8192>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
+    case 16384: launch_range_cap<16384>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
+    case 32768: launch_range_cap<32768>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
