@@ -9,11 +9,11 @@
 //      bit patterns held in LDS (products 3*5*7*11*13, 17*19*23, 29*31),
 //      one funnel shift per pattern per word, no atomics;
 //   2. dense primes (37 <= p < dense_limit): one wavefront per prime.  Only
-//      the multiples p*m with 3 not dividing m are crossed off (3 | m is
-//      already covered by the pre-sieve); over the odd m these form 64
-//      classes modulo 96 odd steps, one per lane.  96*p bits is a whole
-//      number of words (3p), so a lane's bit inside its word never changes
-//      and its word moves by 3p per mark: one LDS atomic OR and one add;
+//      the multiples p*m with m prime to 15 are crossed off (3 | m or 5 | m
+//      is already covered by the pre-sieve); over the odd m these form 256
+//      classes modulo 480 odd steps, four per lane.  480*p bits is a whole
+//      number of words (15p), so a class's bit inside its word never changes
+//      and its word moves by 15p per mark: one LDS atomic OR and one add;
 //   3. sparse primes: one lane per prime walks the multiples p*m with m
 //      prime to 15 (a wheel of period 30, gaps 6,4,2,4,2,4,6,2), so 8 of
 //      every 15 odd multiples are visited.
@@ -146,44 +146,6 @@ __device__ __forceinline__ Start first_multiple(uint64_t n0, double nf, uint32_t
     return s;
 }
 
-// Dense marking of one prime by a whole wavefront.  The odd multiples
-// m0 + 2i (in units of p) with i = m0 (mod 3) are multiples of 3p and are
-// skipped; lane l takes the l-th remaining class c_l of i modulo 96 and marks
-// i = c_l, c_l + 96, c_l + 192, ...  A lane's first word is (s + c_l*p) >> 5
-// and each mark moves it by 96*p bits = 3p words at a fixed bit.  Lane 63 has
-// the largest class and lanes start less than 3p words apart, so the loop is
-// driven by lane 63's word (a scalar) and each lane needs at most one guarded
-// extra mark.
-__device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t p, uint32_t s,
-                                           uint32_t m30, uint32_t lane)
-{
-    const uint32_t r3 = m30 % 3u;  // skip i = r3 (mod 3)
-    const uint32_t a = r3 == 1 ? 1u : 0u;
-    const uint32_t b = r3 == 0 ? 1u : 0u;
-    const uint32_t c = lane + ((lane + a) >> 1) + b;
-    const uint32_t o = s + c * p;
-    const uint32_t mask = 1u << (o & 31);
-    uint32_t *ptr = seg + (o >> 5);
-    const uint32_t step = 3 * p;
-    uint32_t w = (s + (94u + a + b) * p) >> 5;  // lane 63: c = 63 + ((63 + a) >> 1) + b
-    for (; w + 3 * step < sw; w += 4 * step) {
-        uint32_t *p1 = ptr + step;
-        uint32_t *p2 = p1 + step;
-        uint32_t *p3 = p2 + step;
-        lds_or(ptr, mask);
-        lds_or(p1, mask);
-        lds_or(p2, mask);
-        lds_or(p3, mask);
-        ptr = p3 + step;
-    }
-    for (; w < sw; w += step) {
-        lds_or(ptr, mask);
-        ptr += step;
-    }
-    if (ptr < seg + sw)
-        lds_or(ptr, mask);
-}
-
 // Step from the odd multiple at bit offset o (multiplier m, m mod 30 = m30)
 // to the first one whose multiplier is prime to 15 (at most two odd steps);
 // returns the multiplier's position in the cycle of the eight wheel
@@ -195,6 +157,57 @@ __device__ __forceinline__ uint32_t wheel_start(uint32_t p, uint32_t &o, uint32_
         o += p;
     }
     return __popc(kWheelMask & ((1u << m30) - 1u)) & 7u;
+}
+
+// Dense marking of one prime by a whole wavefront.  Only the odd multiples
+// p*m with m prime to 15 are crossed off (3 | m or 5 | m is already covered
+// by the pre-sieve).  Counting odd multiples i = 0, 1, ... from the first
+// such m, the kept i repeat with period 15 (8 per period), so over 480 odd
+// steps there are 256 kept classes: lane l takes c_l + 120 j, j = 0..3,
+// where c_l is the l-th kept class below 120.  480*p bits is a whole number
+// of words (15p), so each of a lane's four classes keeps a fixed bit and
+// moves by 15p words per mark: one LDS atomic OR and one add.  Lane 63 has
+// the largest class, so its fourth class drives the loop (a scalar), and each
+// lane needs at most four guarded marks after it.
+__device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t p, uint32_t s,
+                                           uint32_t m30, uint32_t lane)
+{
+    uint32_t o = s;
+    const uint32_t idx = wheel_start(p, o, m30);
+    const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
+    // c_l = 15 (l / 8) + (sum of the first l mod 8 gaps of the rotated cycle)
+    const uint32_t first = g & ((1u << (2 * (lane & 7))) - 1);
+    const uint32_t e = __popc(first & 0x5555u) + 2 * __popc(first & 0xaaaau);
+    const uint32_t c = 15 * (lane >> 3) + e;
+    const uint32_t c63 = 105 + 15 - ((g >> 14) & 3);  // the eight gaps sum to 15
+    const uint32_t q = 120 * p;                       // bits between a lane's classes
+    const uint32_t x0 = o + c * p;
+    const uint32_t x1 = x0 + q, x2 = x1 + q, x3 = x2 + q;
+    uint32_t *p0 = seg + (x0 >> 5);
+    uint32_t *p1 = seg + (x1 >> 5);
+    uint32_t *p2 = seg + (x2 >> 5);
+    uint32_t *p3 = seg + (x3 >> 5);
+    const uint32_t m0 = 1u << (x0 & 31), m1 = 1u << (x1 & 31), m2 = 1u << (x2 & 31), m3 = 1u << (x3 & 31);
+    const uint32_t step = 15 * p;
+    for (uint32_t top = (o + c63 * p + 3 * q) >> 5; top < sw; top += step) {
+        lds_or(p0, m0);
+        lds_or(p1, m1);
+        lds_or(p2, m2);
+        lds_or(p3, m3);
+        p0 += step;
+        p1 += step;
+        p2 += step;
+        p3 += step;
+    }
+    uint32_t *const end = seg + sw;
+    if (p0 < end)
+        lds_or(p0, m0);
+    if (p1 < end)
+        lds_or(p1, m1);
+    if (p2 < end)
+        lds_or(p2, m2);
+    if (p3 < end)
+        lds_or(p3, m3);
 }
 
 // Sparse marking of one prime by one lane: the multiples p*m with m prime to

@@ -309,6 +309,33 @@ def test_batch_workload_counts(gpu, oracle_mod):
         assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), i
 
 
+def test_batch_workload_bitmaps(gpu, oracle_mod):
+    # the full 4096-interval batched workload with packed bitmaps (2.8 GB on
+    # the device): every interval shorter than 1e6 and a seeded 10% of the
+    # rest are compared word for word, and every count against its bitmap
+    from paper_1205_4883_amd import workloads
+
+    los, his = workloads.batch_intervals(0)
+    print("case batch workload seed 0 with bitmaps", flush=True)
+    pi, words, offs = gpu.batch(los, his, want_bitmap=True)
+    lens = his - los
+    pick = np.zeros(len(los), dtype=bool)
+    pick[lens < 10**6] = True
+    rest = np.nonzero(~pick)[0]
+    pick[np.random.default_rng(12345).choice(rest, size=len(los) // 10, replace=False)] = True
+    checked = 0
+    for i in np.nonzero(pick)[0]:
+        lo, hi = int(los[i]), int(his[i])
+        ref, ref_pi = oracle_mod.bitmap(lo, hi)
+        o = int(offs[i])
+        got = words[o:o + ref.size].cpu().numpy().view(np.uint32)
+        assert int(pi[i]) == ref_pi, (i, lo, hi)
+        assert np.array_equal(got, ref), (i, lo, hi)
+        checked += 1
+    assert checked >= 410
+    del words
+
+
 # -- large-prime hit buckets ---------------------------------------------------
 
 @pytest.mark.parametrize("lo,hi,seg_bits,limit,depth", [
