@@ -114,6 +114,21 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
            "inputs_sha256": workloads.fingerprint(los, his),
            "ms_per_batch": 1e3 * t_batch, "graph_ms": float(np.mean(kms)),
            "ints_per_s": ints / t_batch, "pi_sum": int(pi.sum())}
+    # roofline of the batch graph (reset, batch kernel, reduction, counts
+    # copy; the batch kernel dominates): the intervals' algorithmic LDS work
+    # over the graph's event-timed duration
+    primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(float(his.max()))) + 2)
+    marks = lane_ops = 0
+    for lo, hi in zip(los.tolist(), his.tolist()):
+        m, l, _ = algorithmic_lds_ops(primes, lo, hi)
+        marks += m
+        lane_ops += l
+    g_ms = rec["graph_ms"]
+    rec["roofline"] = {
+        "bound": "lds", "achieved": lane_ops / (g_ms * 1e-3) / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
+        "unit": "Glane-op/s", "frac": lane_ops / (g_ms * 1e-3) / LDS_PEAK_LANE_OPS,
+        "traffic": load_traffic("c4"), "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms,
+        "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": total}}
     if check_plain:
         # the same outputs, one plain call per interval (pi returned per call)
         base = words.data_ptr()
@@ -231,6 +246,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain comparison in the default line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="c4: skip the 4096 one-at-a-time calls (e.g. under a profiler)")
     ap.add_argument("--seg-bits", type=int, default=0, help="tuning: odd integers per segment")
     ap.add_argument("--dense-limit", type=int, default=0, help="tuning: wave-per-prime bound")
     ap.add_argument("--block-threads", type=int, default=0, help="tuning: threads per workgroup")
@@ -284,7 +301,7 @@ def main():
         if args.seg_bits or args.dense_limit or args.block_threads:
             s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
                      block_threads=args.block_threads)
-        b = run_batch(sv, torch, s, args.steps, args.warmup)
+        b = run_batch(sv, torch, s, args.steps, args.warmup, check_plain=not args.no_plain)
         s.close()
         print(json.dumps({
             "metric": METRIC, "value": b["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
