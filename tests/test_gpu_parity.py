@@ -336,6 +336,29 @@ def test_batch_workload_bitmaps(gpu, oracle_mod):
     del words
 
 
+def test_autotune_single_range_and_batch(gpu, oracle_mod, sv_mod):
+    # the tuner times its candidates, applies the winner, caches it, and the
+    # results under the chosen tuning stay exact
+    lo, hi = 10**9, 10**9 + 2 * 10**8
+    try:
+        t, ms = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi])
+        assert ms > 0 and t["seg_bits"] in (1 << 17, 1 << 18, 1 << 19, 1 << 20)
+        assert t["block_threads"] in (512, 1024) and t["dense_limit"] >= 37
+        assert gpu.tuning()["seg_bits"] == t["seg_bits"]
+        t2, ms2 = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi], apply=False)
+        assert t2 == t and ms2 == ms  # cache hit
+        assert gpu.count(lo, hi) == oracle_mod.count(lo, hi)
+        rng = np.random.default_rng(21)
+        los = np.floor(np.exp(rng.uniform(np.log(1e6), np.log(1e11), 64))).astype(np.uint64)
+        his = los + np.floor(np.exp(rng.uniform(np.log(1e4), np.log(1e7), 64))).astype(np.uint64)
+        tb, _ = sv_mod.sieve_autotune(gpu.ctx, los, his)
+        pi = gpu.batch(los, his)
+        for i in range(len(los)):
+            assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), (tb, i)
+    finally:
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0)
+
+
 # -- large-prime hit buckets ---------------------------------------------------
 
 @pytest.mark.parametrize("lo,hi,seg_bits,limit,depth", [
