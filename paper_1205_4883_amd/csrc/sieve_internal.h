@@ -13,8 +13,8 @@ namespace sv {
 constexpr uint32_t kPresievePrimes = 10;
 constexpr uint32_t kFirstMarkedPrime = 37;
 // LDS words taken by the three pre-sieve tables (each is its pattern's
-// period plus one spare word, rounded so the segment starts 16-byte aligned).
-constexpr uint32_t kTableWords = 736;
+// period plus two spare words, rounded so the segment starts 16-byte aligned).
+constexpr uint32_t kTableWords = 740;
 // The bootstrap kernel sieves the odd integers below 2^16 in one workgroup.
 constexpr uint32_t kBootstrapLimit = 65536;
 constexpr uint32_t kBootstrapOddPrimes = 6541;  // odd primes below 2^16

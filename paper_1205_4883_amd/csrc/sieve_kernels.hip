@@ -36,11 +36,11 @@ namespace {
 constexpr uint32_t kLA = 3u * 5u * 7u * 11u * 13u;  // 15015
 constexpr uint32_t kLB = 17u * 19u * 23u;           // 7429
 constexpr uint32_t kLC = 29u * 31u;                 // 899
-// A table of period L holds bits x in [0, L + 63): enough for a 64-bit window
-// starting at any phase j < L.
-constexpr uint32_t kWA = (kLA - 1) / 32 + 2;  // 471
-constexpr uint32_t kWB = (kLB - 1) / 32 + 2;  // 234
-constexpr uint32_t kWC = (kLC - 1) / 32 + 2;  // 30
+// A table of period L holds the words k <= (L - 1) / 32 + 2: enough for a
+// 96-bit window (two output words) starting at any phase j < L.
+constexpr uint32_t kWA = (kLA - 1) / 32 + 3;  // 472
+constexpr uint32_t kWB = (kLB - 1) / 32 + 3;  // 235
+constexpr uint32_t kWC = (kLC - 1) / 32 + 3;  // 31
 static_assert(kWA + kWB + kWC <= kTableWords, "pre-sieve tables exceed their LDS area");
 
 // Odd residues r mod 30 prime to 15, as a bit mask.
@@ -85,12 +85,13 @@ __device__ void build_tables(uint32_t *tabs)
     build_table(tabs + kWA + kWB, kWC, pc, 2);
 }
 
-// 32 pattern bits starting at phase j of a table: a funnel shift of two
-// consecutive table words.
-__device__ __forceinline__ uint32_t pattern_at(const uint32_t *tab, uint32_t j)
+// 64 pattern bits starting at phase j of a table, as two words: funnel
+// shifts of three consecutive table words.
+__device__ __forceinline__ uint2 pattern2_at(const uint32_t *tab, uint32_t j)
 {
-    const uint32_t k = j >> 5;
-    return __builtin_amdgcn_alignbit(tab[k + 1], tab[k], j);
+    const uint32_t *t = tab + (j >> 5);
+    const uint32_t a = t[0], b = t[1], c = t[2];
+    return make_uint2(__builtin_amdgcn_alignbit(b, a, j), __builtin_amdgcn_alignbit(c, b, j));
 }
 
 // The first odd multiple m0*p of p with m0*p >= n0 and m0 >= p (crossing off
@@ -343,23 +344,30 @@ __device__ __forceinline__ SegGeom seg_geom(uint64_t seg, uint32_t seg_words_max
 }
 
 // 1. pre-sieve.  Bit i of the segment is the odd integer 2x + 1 with
-//    x = (n0 >> 1) + i; pattern phases are x mod L.
+//    x = (n0 >> 1) + i; pattern phases are x mod L.  Each thread fills two
+//    adjacent words per step (one 64-bit LDS store), so a phase update and
+//    three table reads serve two words.
 __device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg_lds, const SegGeom &g)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
-    const uint64_t x0 = (g.n0 >> 1) + 32ull * t;
+    const uint64_t x0 = (g.n0 >> 1) + 64ull * t;
     uint32_t ja = static_cast<uint32_t>(x0 % kLA);
     uint32_t jb = static_cast<uint32_t>(x0 % kLB);
     uint32_t jc = static_cast<uint32_t>(x0 % kLC);
-    const uint32_t sa = (32u * nthreads) % kLA;
-    const uint32_t sb = (32u * nthreads) % kLB;
-    const uint32_t sc = (32u * nthreads) % kLC;
+    const uint32_t sa = (64u * nthreads) % kLA;
+    const uint32_t sb = (64u * nthreads) % kLB;
+    const uint32_t sc = (64u * nthreads) % kLC;
     const uint32_t *ta = tabs;
     const uint32_t *tb = tabs + kWA;
     const uint32_t *tc = tabs + kWA + kWB;
-    for (uint32_t w = t; w < g.sw; w += nthreads) {
-        seg_lds[w] = pattern_at(ta, ja) | pattern_at(tb, jb) | pattern_at(tc, jc);
+    for (uint32_t w = 2 * t; w < g.sw; w += 2 * nthreads) {
+        const uint2 a = pattern2_at(ta, ja), b = pattern2_at(tb, jb), c = pattern2_at(tc, jc);
+        const uint2 v = make_uint2(a.x | b.x | c.x, a.y | b.y | c.y);
+        if (w + 1 < g.sw)
+            *reinterpret_cast<uint2 *>(seg_lds + w) = v;  // w even: 8-byte aligned
+        else
+            seg_lds[w] = v.x;
         ja += sa;
         ja = min(ja, ja - kLA);  // unsigned: subtract L once if ja >= L
         jb += sb;
@@ -491,7 +499,7 @@ template <uint32_t kSegMax, bool kWrite>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) range_kernel(
     RangeArgs r, PrimeArgs pa, uint32_t seg_words, uint32_t n_segments, uint32_t chunk, uint32_t n_chunks)
 {
-    __shared__ uint32_t lds[kTableWords + kSegMax];
+    __shared__ __align__(16) uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
     __shared__ unsigned long long red[16];
     uint32_t *tabs = lds;
@@ -567,7 +575,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     BatchHeader *hdr, const uint32_t *primes, const double *inv, uint32_t *words,
     uint32_t *item_counts, uint32_t seg_words)
 {
-    __shared__ uint32_t lds[kTableWords + kSegMax];
+    __shared__ __align__(16) uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
     __shared__ uint32_t red[16];
     uint32_t *tabs = lds;

@@ -156,6 +156,26 @@ def test_tuning_sweep(gpu, oracle_mod, seg_bits, dense_limit, threads):
         gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0)
 
 
+@pytest.mark.parametrize("lo,hi,seg_bits,threads,dense_limit", [
+    (2, 2 * 10**8, 4096, 256, 0),             # carried primes whose p*p falls inside a run
+    (10**9 + 3, 10**9 + 2 * 10**8, 4096, 512, 0),
+    (0, 3 * 10**8, 16384, 1024, 37),          # no dense primes: every prime carried or scanned
+    (10**12 + 1, 10**12 + 4 * 10**8, 8192, 256, 0),  # runs inside bucket windows
+])
+def test_runs_of_segments_with_carried_offsets(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, threads,
+                                               dense_limit):
+    # small segments give launches with many more segments than workgroups, so
+    # work items are runs of consecutive segments and lanes carry their
+    # primes' next multiples from segment to segment
+    gpu.tuning(seg_bits=seg_bits, block_threads=threads, dense_limit=dense_limit)
+    try:
+        plan = sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())
+        assert plan["n_segments"] > 9000
+        _cmp_bitmap(gpu, oracle_mod, lo, hi)
+    finally:
+        gpu.tuning(seg_bits=0, block_threads=0, dense_limit=0)
+
+
 def test_additivity_on_gpu(gpu):
     rng = random.Random(7)
     for _ in range(30):
