@@ -67,18 +67,20 @@ typedef struct sieve_ctx sieve_ctx;
  *   seg_bits      odd integers per LDS segment (a multiple of 4096, at most
  *                 what one workgroup's LDS holds).
  *   dense_limit   base primes below this are marked by a whole wavefront per
- *                 prime (64 lanes on 64 consecutive multiples); primes at or
- *                 above it by one lane per prime.  Clamped to >= 37.
+ *                 prime (each lane on four residue classes of the multiples);
+ *                 primes at or above it by one lane per prime.  Clamped to
+ *                 >= 37; automatic: max(seg_bits / 512, 128).
  *   bucket_limit  base primes at or above this (and at least seg_bits) are
  *                 not scanned per segment: a fill kernel first sorts their
  *                 hits into per-segment buckets in HBM, which the segment
  *                 kernel then applies (plain path).  0 = automatic (buckets
- *                 when sqrt(hi) >= 2 * seg_bits), 0xFFFFFFFF = never.
+ *                 when sqrt(hi) >= 1.5 * seg_bits), 0xFFFFFFFF = never.
  *   bucket_depth  entries per segment bucket (0 = from the expected hits
  *                 plus six standard deviations).  A bucket that overflows is
  *                 detected and the call is redone with twice the depth, so
  *                 results never depend on it.
- *   block_threads threads per workgroup: 256, 512 or 1024.
+ *   block_threads threads per workgroup: 256, 512 or 1024 (automatic: 1024
+ *                 from 2^19-bit segments, 512 from 2^14, else 256).
  *   wg_per_cu     resident workgroups per compute unit for persistent
  *                 launches (0 = as many as LDS allows). */
 typedef struct sieve_tuning {

@@ -66,6 +66,15 @@ uint32_t default_threads(uint32_t sw)
     return sw >= 16384 ? 1024u : (sw >= 512 ? 512u : 256u);
 }
 
+// Primes below the dense limit are marked a wavefront per prime: seg_bits /
+// 512 (a prime there has at least ~500 multiples in the segment), but at
+// least 128, so that on small segments the smallest primes' long walks are
+// spread over a wavefront instead of one lane.
+uint32_t default_dense_limit(uint32_t seg_bits)
+{
+    return std::max(seg_bits / 512, 128u);
+}
+
 int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
               sieve_plan_info *out)
 {
@@ -100,7 +109,7 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         sw = static_cast<uint32_t>(std::min<uint64_t>(pw, cap));
     }
     p.seg_bits = sw * 32;
-    p.dense_limit = t.dense_limit ? t.dense_limit : p.seg_bits / 512;
+    p.dense_limit = t.dense_limit ? t.dense_limit : default_dense_limit(p.seg_bits);
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
     p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
@@ -119,8 +128,12 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     return SIEVE_OK;
 }
 
-// The next per-call counter slot, once its previous user has finished.
-int take_slot(sieve_ctx *c, uint32_t **words)
+// The next per-call counter slot, once its previous user has finished.  A
+// slot is all zero between calls (each call's last launch leaves it so); a
+// call that failed before its launches were all enqueued left it dirty, and
+// it is cleared on s first.  The caller marks the slot dirty until its last
+// launch is enqueued.
+int take_slot(sieve_ctx *c, hipStream_t s, uint32_t **words)
 {
     const int i = c->next_slot;
     c->next_slot = (i + 1) % sieve_ctx::kSlots;
@@ -128,25 +141,20 @@ int take_slot(sieve_ctx *c, uint32_t **words)
         HIP_TRY(c, hipEventSynchronize(c->slot_done[i]));
     c->slot_used[i] = false;
     *words = c->d_ctr + static_cast<size_t>(i) * kCounterWords;
+    if (c->slot_dirty[i])
+        HIP_TRY(c, hipMemsetAsync(*words, 0, kCounterWords * sizeof(uint32_t), s));
+    c->slot_dirty[i] = true;
     return i;
 }
 
-constexpr size_t kQueueBytes = kQueues * kLineWords * sizeof(uint32_t);  // the queue lines of a slot
-constexpr size_t kCountBytes = kQueueBytes;                              // the count lines
+// The pinned word the last launch of a call publishes its count to: reset
+// to a value no count can take before the launch, read after the stream
+// synchronises.
+constexpr uint64_t kUnpublished = ~0ull;
 
-// Copy a slot's count lines to the pinned mirror (asynchronous on s).
-hipError_t fetch_counts(sieve_ctx *c, const uint32_t *slot, hipStream_t s)
+volatile uint64_t *published(sieve_ctx *c)
 {
-    return hipMemcpyAsync(c->h_ctr, slot + kQueues * kLineWords, kCountBytes, hipMemcpyDeviceToHost, s);
-}
-
-// Sum of the partial counts in the pinned mirror (once the copy completed).
-uint64_t mirrored_count(const sieve_ctx *c)
-{
-    uint64_t total = 0;
-    for (uint32_t q = 0; q < kQueues; ++q)
-        total += *reinterpret_cast<const uint64_t *>(c->h_ctr + q * kLineWords);
-    return total;
+    return reinterpret_cast<volatile uint64_t *>(c->h_ctr);
 }
 
 // Workgroups that fit on the device at once for a plan.
@@ -218,21 +226,17 @@ int build_primes(sieve_ctx *c, uint64_t limit)
             break;
         }
         uint32_t *slot = nullptr;
-        const int si = take_slot(c, &slot);
+        const int si = take_slot(c, s, &slot);
         if (si < 0) {
             st = si;
             break;
         }
-        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, slot, false, nullptr, nullptr, 0};
-        e = hipMemsetAsync(slot, 0, kQueueBytes, s);
-        if (e != hipSuccess) {
-            c->last_hip = e;
-            st = SIEVE_EDEVICE;
-            break;
-        }
+        sv::RangeArgs ra{1, pl.nbits, pl.n_words, d_words, slot, false, true, nullptr, nullptr, nullptr, 0};
         sv::PrimeArgs pa{d_boot + sv::kPresievePrimes, d_boot_inv + sv::kPresievePrimes, n_dense, n_mark};
         e = sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
                              static_cast<uint32_t>(pl.n_segments), resident_blocks(c, pl, true), s);
+        if (e == hipSuccess)
+            c->slot_dirty[si] = false;
         if (e == hipSuccess)
             e = hipEventRecord(c->slot_done[si], s);
         c->slot_used[si] = true;
@@ -362,11 +366,11 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
         uint32_t *bcount = static_cast<uint32_t *>(c->b_bcount.p);
         uint32_t *overflow = bcount + win;
         uint32_t *slot = nullptr;
-        const int si = take_slot(c, &slot);
+        const int si = take_slot(c, s, &slot);
         if (si < 0)
             return si;
-        HIP_TRY(c, hipMemsetAsync(slot + kQueues * kLineWords, 0, kCountBytes, s));
         HIP_TRY(c, hipMemsetAsync(overflow, 0, sizeof(uint32_t), s));
+        *published(c) = kUnpublished;
         c->ev_valid = false;
         HIP_TRY(c, hipEventRecord(c->ev_start, s));
         for (uint64_t w0 = 0; w0 < pl.n_segments; w0 += win) {
@@ -375,12 +379,13 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
             const uint64_t bits_w = std::min<uint64_t>(static_cast<uint64_t>(segs) * pl.seg_bits, pl.nbits - word0 * 32);
             const uint64_t fo = first_odd + 64 * word0;
             HIP_TRY(c, hipMemsetAsync(bcount, 0, segs * sizeof(uint32_t), s));
-            HIP_TRY(c, hipMemsetAsync(slot, 0, kQueueBytes, s));
             HIP_TRY(c, sv::launch_bucket_fill(c->d_primes + kPresievePrimes + n_small,
                                               c->d_inv + kPresievePrimes + n_small, n_large, fo, seg_log2, segs,
                                               buckets, bcount, static_cast<uint32_t>(depth), overflow, s));
+            const bool last = w0 + win >= pl.n_segments;
             sv::RangeArgs ra{fo, bits_w, (bits_w + 31) / 32, d_words ? d_words + word0 : nullptr,
-                             slot, pi_out != nullptr, buckets, bcount, static_cast<uint32_t>(depth)};
+                             slot, pi_out != nullptr, last, pi_out && last ? c->d_pub : nullptr,
+                             buckets, bcount, static_cast<uint32_t>(depth)};
             sv::PrimeArgs pa{c->d_primes + kPresievePrimes, c->d_inv + kPresievePrimes, std::min(n_dense, n_small),
                              n_small};
             sieve_plan_info wp = pl;
@@ -388,18 +393,21 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
             HIP_TRY(c, sv::launch_range(ra, pa, sw, pl.block_threads, segs,
                                         resident_blocks(c, wp, d_words != nullptr), s));
         }
+        c->slot_dirty[si] = false;
         HIP_TRY(c, hipEventRecord(c->ev_stop, s));
         c->ev_valid = true;
-        uint32_t *h_flag = c->h_ctr + kQueues * kLineWords;
-        if (pi_out)
-            HIP_TRY(c, fetch_counts(c, slot, s));
+        uint32_t *h_flag = c->h_ctr + 16;
         HIP_TRY(c, hipMemcpyAsync(h_flag, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
         c->slot_used[si] = true;
         HIP_TRY(c, hipStreamSynchronize(s));
         if (*h_flag == 0) {
-            if (pi_out)
-                *pi_out = mirrored_count(c);  // odd primes only
+            if (pi_out) {
+                const uint64_t v = *published(c);
+                if (v == kUnpublished)
+                    return SIEVE_EDEVICE;
+                *pi_out = v;  // odd primes only
+            }
             return SIEVE_OK;
         }
         if (depth >= (1ull << 26))
@@ -438,27 +446,30 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
         return SIEVE_OK;
     }
     uint32_t *slot = nullptr;
-    const int si = take_slot(c, &slot);
+    const int si = take_slot(c, s, &slot);
     if (si < 0)
         return si;
-    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, pi_out != nullptr,
-                     nullptr, nullptr, 0};
+    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, pi_out != nullptr, true,
+                     pi_out ? c->d_pub : nullptr, nullptr, nullptr, 0};
     sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
-    HIP_TRY(c, hipMemsetAsync(slot, 0, kCounterWords * sizeof(uint32_t), s));
+    if (pi_out)
+        *published(c) = kUnpublished;
     c->ev_valid = false;
     HIP_TRY(c, hipEventRecord(c->ev_start, s));
     HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
                                 static_cast<uint32_t>(pl.n_segments),
                                 resident_blocks(c, pl, d_words != nullptr), s));
+    c->slot_dirty[si] = false;
     HIP_TRY(c, hipEventRecord(c->ev_stop, s));
     c->ev_valid = true;
-    if (pi_out)
-        HIP_TRY(c, fetch_counts(c, slot, s));
     HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
     c->slot_used[si] = true;
     if (pi_out) {
         HIP_TRY(c, hipStreamSynchronize(s));
-        *pi_out = mirrored_count(c) + two;
+        const uint64_t v = *published(c);
+        if (v == kUnpublished)
+            return SIEVE_EDEVICE;
+        *pi_out = v + two;
     }
     return SIEVE_OK;
 }
@@ -605,7 +616,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
         return st;
     const uint32_t cap = std::min(max_seg_words(c->lds_max), kDefaultMaxSegWords);
     const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
-    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : sw * 32 / 512,
+    const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : default_dense_limit(sw * 32),
                                           sv::kFirstMarkedPrime);
     const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : default_threads(sw);
     std::vector<std::pair<uint64_t, uint64_t>> spans;
@@ -804,8 +815,13 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
     for (int i = 0; i < sieve_ctx::kSlots && e == hipSuccess; ++i)
         e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
     if (e == hipSuccess)
-        e = hipHostMalloc(&c->h_ctr, (sv::kQueues * sv::kLineWords + 64) * sizeof(uint32_t),
-                          hipHostMallocDefault);
+        e = hipHostMalloc(&c->h_ctr, 64 * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess)
+        e = hipHostGetDevicePointer(reinterpret_cast<void **>(&c->d_pub), c->h_ctr, 0);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_ctr, 0, sieve_ctx::kSlots * sv::kCounterWords * sizeof(uint32_t), c->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
         e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess)

@@ -23,16 +23,22 @@ constexpr uint32_t kBootstrapOddPrimes = 6541;  // odd primes below 2^16
 // one address serialise across the chip (measured at about 12 ns apiece on
 // MI355X, enough to bound a whole launch when every wave adds its count per
 // segment), so a launch spreads them over kQueues work counters and kQueues
-// partial counts, each alone in a 256-byte line:
+// count lines, each alone in a 256-byte line, plus one grid word:
 //   queue q (uint32_t) at word q * kLineWords,
-//   count q (uint64_t) at word (kQueues + q) * kLineWords.
+//   count line q (uint64_t: count << 16 | workgroups added) at word
+//     (kQueues + q) * kLineWords,
+//   grid word (uint64_t: count << 8 | lines completed) at word kDoneWord.
 // Work queue q hands out the items k * kQueues + q, k = 0, 1, ...; workgroup
 // b starts on queue b mod kQueues and moves on to the next queue when its own
 // runs dry, so every item is taken exactly once whatever the grid size, and
 // each workgroup makes at most kQueues failed pops before it leaves.
+// A range launch leaves its counter block all zero (the grid word keeps the
+// running count between the launches of one call): the workgroup that
+// completes the grid word resets it and publishes the count.
 constexpr uint32_t kQueues = 8;
 constexpr uint32_t kLineWords = 64;
-constexpr uint32_t kCounterWords = 2 * kQueues * kLineWords;
+constexpr uint32_t kDoneWord = 2 * kQueues * kLineWords;
+constexpr uint32_t kCounterWords = (2 * kQueues + 1) * kLineWords;
 
 // One range as the segment kernels see it.
 struct RangeArgs {
@@ -40,8 +46,10 @@ struct RangeArgs {
     uint64_t nbits;      // odd integers in the range
     uint64_t n_words;    // ceil(nbits / 32)
     uint32_t *out;       // bitmap words of the range (word 0 = bit 0), or null
-    uint32_t *counters;  // kCounterWords words; the queues are zero at launch
-    bool count;          // add the number of 1 bits (primes) to the counts
+    uint32_t *counters;  // kCounterWords words, all zero at launch
+    bool count;          // count the 1 bits (primes)
+    bool last;           // the call's last launch: publish the count and clear it
+    unsigned long long *publish;  // where the last launch stores the count (host-mapped), or null
     // Large-prime hit buckets of this launch's segments, or null: segment s
     // owns buckets[s * bucket_depth ..) with min(bucket_count[s], depth)
     // entries, each a bit offset inside the segment.

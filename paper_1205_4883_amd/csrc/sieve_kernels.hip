@@ -28,6 +28,8 @@
 // wave is served separately) sets the cost of the scattered atomic ORs; the
 // wheel cuts their number, and the fixed-bit lane layout keeps the VALU work
 // per dense mark at one add.
+#include <atomic>
+
 #include "sieve_internal.h"
 
 namespace sv {
@@ -58,31 +60,47 @@ __device__ __forceinline__ void lds_or(uint32_t *word, uint32_t mask)
     __hip_atomic_fetch_or(word, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Bit b of table word k stands for the odd integer 2(32k + b) + 1 and is set
-// when one of the group's primes divides it: p | 2x + 1 <=> x = (p-1)/2 mod p.
-__device__ void build_table(uint32_t *tab, uint32_t n_words, const uint32_t *ps, int np)
+// The three pre-sieve tables, computed at compile time.  Bit b of a table's
+// word k stands for the odd integer 2(32k + b) + 1 and is set when one of
+// the group's primes divides it.
+struct PresieveTables {
+    uint32_t w[kTableWords];
+};
+
+constexpr uint32_t table_word(uint32_t k, const uint32_t *ps, int np)
 {
-    for (uint32_t k = threadIdx.x; k < n_words; k += blockDim.x) {
-        uint32_t m = 0;
-        for (int i = 0; i < np; ++i) {
-            uint32_t p = ps[i];
-            uint32_t x0 = 32u * k;
-            uint32_t b = ((p - 1) / 2 + p - x0 % p) % p;  // first bit with x = (p-1)/2 mod p
-            for (; b < 32; b += p)
+    uint32_t m = 0;
+    for (uint32_t b = 0; b < 32; ++b) {
+        const uint32_t odd = 2 * (32 * k + b) + 1;
+        for (int i = 0; i < np; ++i)
+            if (odd % ps[i] == 0)
                 m |= 1u << b;
-        }
-        tab[k] = m;
     }
+    return m;
 }
 
-__device__ void build_tables(uint32_t *tabs)
+constexpr PresieveTables make_tables()
 {
-    const uint32_t pa[5] = {3, 5, 7, 11, 13};
-    const uint32_t pb[3] = {17, 19, 23};
-    const uint32_t pc[2] = {29, 31};
-    build_table(tabs, kWA, pa, 5);
-    build_table(tabs + kWA, kWB, pb, 3);
-    build_table(tabs + kWA + kWB, kWC, pc, 2);
+    constexpr uint32_t pa[5] = {3, 5, 7, 11, 13};
+    constexpr uint32_t pb[3] = {17, 19, 23};
+    constexpr uint32_t pc[2] = {29, 31};
+    PresieveTables t{};
+    for (uint32_t k = 0; k < kWA; ++k)
+        t.w[k] = table_word(k, pa, 5);
+    for (uint32_t k = 0; k < kWB; ++k)
+        t.w[kWA + k] = table_word(k, pb, 3);
+    for (uint32_t k = 0; k < kWC; ++k)
+        t.w[kWA + kWB + k] = table_word(k, pc, 2);
+    return t;
+}
+
+__constant__ PresieveTables kTables = make_tables();
+
+// Copy the tables into the workgroup's LDS (visible after its next barrier).
+__device__ __forceinline__ void build_tables(uint32_t *tabs)
+{
+    for (uint32_t k = threadIdx.x; k < kTableWords; k += blockDim.x)
+        tabs[k] = kTables.w[k];
 }
 
 // 64 pattern bits starting at phase j of a table, as two words: funnel
@@ -303,22 +321,19 @@ __device__ __forceinline__ uint32_t pop_item(uint32_t *counters, uint32_t &q, ui
     return kNoItem;
 }
 
-// Sum of every thread's v, added once per workgroup to *dst (red: one LDS
-// word per wavefront).
-__device__ __forceinline__ void block_add(unsigned long long v, unsigned long long *dst,
-                                          unsigned long long *red)
+// Sum of every thread's v over the workgroup, valid in thread 0 (red: one
+// LDS word per wavefront).
+__device__ __forceinline__ unsigned long long wg_sum(unsigned long long v, unsigned long long *red)
 {
     v = wave_sum64(v);
     if ((threadIdx.x & 63) == 0)
         red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long total = 0;
+    unsigned long long total = 0;
+    if (threadIdx.x == 0)
         for (uint32_t w = 0; w < (blockDim.x >> 6); ++w)
             total += red[w];
-        if (total)
-            atomicAdd(dst, total);
-    }
+    return total;
 }
 
 // Where one segment of a range lies.
@@ -458,6 +473,42 @@ __device__ __forceinline__ uint32_t seg_count(uint32_t *seg_lds, const SegGeom &
     return c;
 }
 
+// Thread 0 of each workgroup, as it leaves, with the workgroup's count.  The
+// count and the "finished" tally travel in one read-modify-write each, so no
+// fence is needed: workgroup b adds (count << 16) | 1 to count line
+// b mod kQueues; the workgroup whose add completes its line (the returned
+// tally shows it was the line's last) adds (line total << 8) | 1 to the grid
+// word; and the one that completes the grid word holds the launch's total in
+// the returned value.  It then returns the counter block to zero for the
+// next launch (keeping the running total in the grid word between the
+// launches of one call) and, on the call's last launch, publishes the total.
+__device__ void finish_launch(const RangeArgs &r, unsigned long long wg_count)
+{
+    const uint32_t grid = gridDim.x;
+    const uint32_t q = blockIdx.x % kQueues;
+    const uint32_t in_line = grid / kQueues + (q < grid % kQueues ? 1u : 0u);
+    const uint32_t lines = grid < kQueues ? grid : kQueues;
+    auto *line = reinterpret_cast<unsigned long long *>(r.counters + (kQueues + q) * kLineWords);
+    const unsigned long long old = atomicAdd(line, (wg_count << 16) | 1ull);
+    if ((old & 0xffffu) + 1 != in_line)
+        return;
+    const unsigned long long line_total = (old >> 16) + wg_count;
+    auto *all = reinterpret_cast<unsigned long long *>(r.counters + kDoneWord);
+    const unsigned long long old2 = atomicAdd(all, (line_total << 8) | 1ull);
+    if ((old2 & 0xffu) + 1 != lines)
+        return;
+    const unsigned long long total = (old2 >> 8) + line_total;
+    // every workgroup has left: no pop or add on this block is still to come
+    for (uint32_t k = 0; k < kQueues; ++k) {
+        __hip_atomic_store(r.counters + k * kLineWords, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(reinterpret_cast<unsigned long long *>(r.counters + (kQueues + k) * kLineWords), 0ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_store(all, r.last ? 0ull : total << 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (r.last && r.publish)
+        *r.publish = total;  // the host reads it after synchronising with the stream
+}
+
 // Sieve segment `seg` of one range into LDS and emit its words; returns the
 // number of primes among this thread's words.  tabs: the pre-sieve tables in
 // LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
@@ -558,10 +609,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             acc += seg_count<kWrite>(seg, g, r.first_odd, r.nbits, r.n_words, r.out);
         }
     }
-    if (r.count)
-        block_add(acc,
-                  reinterpret_cast<unsigned long long *>(r.counters + (kQueues + blockIdx.x % kQueues) * kLineWords),
-                  red);
+    const unsigned long long wg_count = r.count ? wg_sum(acc, red) : 0;
+    if (threadIdx.x == 0)
+        finish_launch(r, wg_count);
 }
 
 // Persistent batch kernel: workgroups pop (interval, segment) items from the
@@ -939,35 +989,70 @@ void launch_batch_cap(BatchHeader *d_blob, const uint32_t *d_primes, const doubl
 
 namespace {
 template <typename K>
-uint32_t blocks_per_cu(K kernel, uint32_t threads)
+uint32_t occupancy(K kernel, uint32_t threads)
 {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, static_cast<int>(threads), 0) != hipSuccess)
         return 1;
     return n > 0 ? static_cast<uint32_t>(n) : 1u;
 }
+
+// The occupancy query costs microseconds and its answer depends only on the
+// kernel and the workgroup size (every device here is a gfx950), so it is
+// asked once per (kernel, threads) and kept; 0 = not asked yet.
+std::atomic<uint32_t> g_occupancy[3][6][17];  // [range count, range bitmap, batch]
+
+uint32_t cap_index(uint32_t cap)
+{
+    switch (cap) {
+    case 512: return 1;
+    case 2048: return 2;
+    case 8192: return 3;
+    case 16384: return 4;
+    case 32768: return 5;
+    default: return 0;
+    }
+}
+
+template <typename K>
+uint32_t blocks_per_cu(K kernel, uint32_t threads, int kind, uint32_t cap)
+{
+    const uint32_t ci = cap_index(cap);
+    if (threads % 64 != 0 || threads > 1024 || ci == 0)
+        return occupancy(kernel, threads);
+    std::atomic<uint32_t> &slot = g_occupancy[kind][ci][threads / 64];
+    uint32_t v = slot.load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = occupancy(kernel, threads);
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
 }  // namespace
 
 uint32_t range_blocks_per_cu(uint32_t seg_words, uint32_t threads, bool write)
 {
-    switch (seg_capacity_for(seg_words)) {
-    case 512: return write ? blocks_per_cu(range_kernel<512, true>, threads) : blocks_per_cu(range_kernel<512, false>, threads);
-    case 2048: return write ? blocks_per_cu(range_kernel<2048, true>, threads) : blocks_per_cu(range_kernel<2048, false>, threads);
-    case 8192: return write ? blocks_per_cu(range_kernel<8192, true>, threads) : blocks_per_cu(range_kernel<8192, false>, threads);
-    case 16384: return write ? blocks_per_cu(range_kernel<16384, true>, threads) : blocks_per_cu(range_kernel<16384, false>, threads);
-    case 32768: return write ? blocks_per_cu(range_kernel<32768, true>, threads) : blocks_per_cu(range_kernel<32768, false>, threads);
+    const uint32_t cap = seg_capacity_for(seg_words);
+    const int kind = write ? 1 : 0;
+    switch (cap) {
+    case 512: return write ? blocks_per_cu(range_kernel<512, true>, threads, kind, cap) : blocks_per_cu(range_kernel<512, false>, threads, kind, cap);
+    case 2048: return write ? blocks_per_cu(range_kernel<2048, true>, threads, kind, cap) : blocks_per_cu(range_kernel<2048, false>, threads, kind, cap);
+    case 8192: return write ? blocks_per_cu(range_kernel<8192, true>, threads, kind, cap) : blocks_per_cu(range_kernel<8192, false>, threads, kind, cap);
+    case 16384: return write ? blocks_per_cu(range_kernel<16384, true>, threads, kind, cap) : blocks_per_cu(range_kernel<16384, false>, threads, kind, cap);
+    case 32768: return write ? blocks_per_cu(range_kernel<32768, true>, threads, kind, cap) : blocks_per_cu(range_kernel<32768, false>, threads, kind, cap);
     default: return 1;
     }
 }
 
 uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
 {
-    switch (seg_capacity_for(seg_words)) {
-    case 512: return blocks_per_cu(batch_kernel<512>, threads);
-    case 2048: return blocks_per_cu(batch_kernel<2048>, threads);
-    case 8192: return blocks_per_cu(batch_kernel<8192>, threads);
-    case 16384: return blocks_per_cu(batch_kernel<16384>, threads);
-    case 32768: return blocks_per_cu(batch_kernel<32768>, threads);
+    const uint32_t cap = seg_capacity_for(seg_words);
+    switch (cap) {
+    case 512: return blocks_per_cu(batch_kernel<512>, threads, 2, cap);
+    case 2048: return blocks_per_cu(batch_kernel<2048>, threads, 2, cap);
+    case 8192: return blocks_per_cu(batch_kernel<8192>, threads, 2, cap);
+    case 16384: return blocks_per_cu(batch_kernel<16384>, threads, 2, cap);
+    case 32768: return blocks_per_cu(batch_kernel<32768>, threads, 2, cap);
     default: return 1;
     }
 }

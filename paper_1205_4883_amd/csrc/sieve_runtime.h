@@ -90,10 +90,12 @@ struct sieve_ctx {
     uint32_t *d_ctr = nullptr;  // kSlots * kCounterWords words
     hipEvent_t slot_done[kSlots] = {};
     bool slot_used[kSlots] = {};
+    bool slot_dirty[kSlots] = {};  // not known to be all zero
     int next_slot = 0;
-    // pinned: the count lines of a slot (kQueues * kLineWords words), then
-    // one spare word (the bucket overflow flag)
+    // pinned and mapped, 64 words: the published count (words 0-1, written
+    // by the kernel through d_pub) and the bucket overflow flag (word 16)
     uint32_t *h_ctr = nullptr;
+    unsigned long long *d_pub = nullptr;
 
     // events bracketing the last sieve kernel launch (range or batch)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;

@@ -78,7 +78,8 @@ def test_plan_tuning_resolution():
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 15))
     assert p["block_threads"] == 512
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 13))
-    assert p["block_threads"] == 256
+    assert p["block_threads"] == 256 and p["dense_limit"] == 128
+    assert sv.sieve_plan(2, 10**7)["dense_limit"] == 128
     # hit buckets: automatic once sqrt(hi) reaches 1.5 segments
     assert sv.sieve_plan(10**12, 10**12 + 10**10)["bucket_limit"] == 1 << 19
     assert sv.sieve_plan(10**11, 10**11 + 10**10)["bucket_limit"] == 0
