@@ -173,7 +173,8 @@ def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
                      "span_s": span,
                      "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
                      "ints_per_s": ints / span, "batches": st["batches"],
-                     "max_batch": st["max_batch_seen"], "max_inflight": st["max_inflight"]}
+                     "max_batch": st["max_batch_seen"], "max_inflight": st["max_inflight"],
+                     "single_launches": st["single_launches"]}
         pis[mode] = pi
     if len(pis) == 2:
         assert np.array_equal(pis["batched"], pis["plain"]), "served results differ by mode"

@@ -74,7 +74,8 @@ typedef struct sieve_ctx sieve_ctx;
  *                 not scanned per segment: a fill kernel first sorts their
  *                 hits into per-segment buckets in HBM, which the segment
  *                 kernel then applies (plain path).  0 = automatic (buckets
- *                 when sqrt(hi) >= 1.5 * seg_bits), 0xFFFFFFFF = never.
+ *                 when sqrt(hi) >= 1.5 * seg_bits and the range holds at
+ *                 least 2^30 odd integers), 0xFFFFFFFF = never.
  *   bucket_depth  entries per segment bucket (0 = from the expected hits
  *                 plus six standard deviations).  A bucket that overflows is
  *                 detected and the call is redone with twice the depth, so
@@ -282,6 +283,7 @@ typedef struct sieve_server_stats {
     uint64_t submitted;
     uint64_t completed;
     uint64_t batches;           /* batches (or plain launches) issued */
+    uint64_t single_launches;   /* batches of one served by the plain range launch */
     uint64_t max_batch_seen;    /* most requests in one batch */
     uint64_t max_inflight;      /* most batches on the device at once */
     uint64_t deferred;          /* admissions that had to wait for budget */

@@ -115,12 +115,15 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.n_segments = (p.n_words + sw - 1) / sw;
     // Hit buckets need power-of-two segments and only pay when the largest
     // base primes skip most segments (measured: from sqrt(hi) of about
-    // 1.9 segments on, e.g. 2.30 -> 1.99 ms for 10^10 integers at 10^12).
+    // 1.9 segments on, e.g. 2.30 -> 1.99 ms for 10^10 integers at 10^12),
+    // and when the range is long enough to amortise the fill launch and the
+    // overflow check's host round trip (at least 2^30 odd integers).
     p.bucket_limit = 0;
     const bool pow2 = (p.seg_bits & (p.seg_bits - 1)) == 0;
     if (t.bucket_limit != 0xffffffffu && pow2 && p.n_segments >= 2) {
         const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
-        const bool want = t.bucket_limit ? true : 2 * p.sqrt_bound >= 3ull * p.seg_bits;
+        const bool want = t.bucket_limit ? true
+                                         : 2 * p.sqrt_bound >= 3ull * p.seg_bits && p.nbits >= (1ull << 30);
         if (want && lim <= p.sqrt_bound && lim < 0xffffffffull)
             p.bucket_limit = static_cast<uint32_t>(lim);
     }
@@ -418,6 +421,40 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
 
 }  // namespace
 
+namespace {
+
+// One plain launch of a planned range without buckets on s: the count of odd
+// primes is published to *d_pub (a device-visible pinned word) when d_pub is
+// not null.  timed: bracket the launch with the context's timing events.
+int enqueue_plain(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uint32_t *d_words,
+                  unsigned long long *d_pub, hipStream_t s, bool timed, uint32_t n_mark, uint32_t n_dense)
+{
+    uint32_t *slot = nullptr;
+    const int si = take_slot(c, s, &slot);
+    if (si < 0)
+        return si;
+    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, d_pub != nullptr, true,
+                     d_pub, nullptr, nullptr, 0};
+    sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
+    if (timed) {
+        c->ev_valid = false;
+        HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    }
+    HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
+                                static_cast<uint32_t>(pl.n_segments),
+                                resident_blocks(c, pl, d_words != nullptr), s));
+    c->slot_dirty[si] = false;
+    if (timed) {
+        HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+        c->ev_valid = true;
+    }
+    HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
+    c->slot_used[si] = true;
+    return SIEVE_OK;
+}
+
+}  // namespace
+
 int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t *pi_out,
               hipStream_t s)
 {
@@ -445,25 +482,10 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
             *pi_out = pi + two;
         return SIEVE_OK;
     }
-    uint32_t *slot = nullptr;
-    const int si = take_slot(c, s, &slot);
-    if (si < 0)
-        return si;
-    sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, pi_out != nullptr, true,
-                     pi_out ? c->d_pub : nullptr, nullptr, nullptr, 0};
-    sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
     if (pi_out)
         *published(c) = kUnpublished;
-    c->ev_valid = false;
-    HIP_TRY(c, hipEventRecord(c->ev_start, s));
-    HIP_TRY(c, sv::launch_range(ra, pa, pl.seg_bits / 32, pl.block_threads,
-                                static_cast<uint32_t>(pl.n_segments),
-                                resident_blocks(c, pl, d_words != nullptr), s));
-    c->slot_dirty[si] = false;
-    HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-    c->ev_valid = true;
-    HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
-    c->slot_used[si] = true;
+    if (int st = enqueue_plain(c, pl, lo, d_words, pi_out ? c->d_pub : nullptr, s, true, n_mark, n_dense))
+        return st;
     if (pi_out) {
         HIP_TRY(c, hipStreamSynchronize(s));
         const uint64_t v = *published(c);
@@ -472,6 +494,22 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
         *pi_out = v + two;
     }
     return SIEVE_OK;
+}
+
+int range_async(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, unsigned long long *d_pub,
+                hipStream_t s)
+{
+    sieve_plan_info pl{};
+    if (int st = make_plan(lo, hi, &c->tuning, c->n_cu, c->lds_max, &pl))
+        return st;
+    if (pl.nbits == 0 || pl.bucket_limit || pl.n_segments > 0xffffffffull)
+        return kNotAsync;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (int st = ensure_primes(c, pl.sqrt_bound))
+        return st;
+    uint32_t n_mark = 0, n_dense = 0;
+    marking_primes(c, pl.sqrt_bound, pl.dense_limit, &n_mark, &n_dense);
+    return enqueue_plain(c, pl, lo, d_words, d_pub, s, false, n_mark, n_dense);
 }
 
 int grow(sieve_ctx *c, DevBuf &b, size_t bytes)

@@ -130,6 +130,14 @@ void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32
 // The plain path: sieve [lo, hi) into d_words (may be null) and/or count it.
 int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_t *pi_out,
               hipStream_t s);
+// The plain path enqueued without waiting, for a caller that tracks
+// completion itself: the launch publishes the count of odd primes (2 not
+// included) to *d_pub, a device-visible pinned word.  Returns kNotAsync,
+// enqueueing nothing, when the range is empty or needs hit buckets (whose
+// overflow check needs a host round trip).
+constexpr int kNotAsync = 1;
+int range_async(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, unsigned long long *d_pub,
+                hipStream_t s);
 int grow(sieve_ctx *c, DevBuf &b, size_t bytes);
 int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes);
 

@@ -109,7 +109,13 @@ struct Lane {
     std::vector<Request *> reqs;
     std::vector<sieve_interval> iv;
     bool busy = false;
+    bool single = false;  // the launch in flight is one plain range launch
+    // pinned and mapped: the count a single launch publishes
+    volatile unsigned long long *h_pub = nullptr;
+    unsigned long long *d_pub = nullptr;
 };
+
+constexpr unsigned long long kUnpublished = ~0ull;
 
 }  // namespace
 
@@ -191,6 +197,28 @@ void take_batch_locked(sieve_server *s, Lane &lane)
     }
 }
 
+// A batch of one goes through the plain range launch, which skips the batch
+// staging, upload and graph (the lowest latency when requests arrive one at
+// a time); the count is published to the lane's pinned word.  Returns
+// sv::kNotAsync when the range is not eligible (empty, or bucketed).
+int launch_single_lane(sieve_server *s, Lane &lane)
+{
+    sieve_ctx *c = s->ctx;
+    Request *r = lane.reqs[0];
+    const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
+    *lane.h_pub = kUnpublished;
+    r->t_launch = now_ns();
+    const int st = sv::range_async(c, r->lo, r->hi, bm ? lane.d_words : nullptr, lane.d_pub, lane.stream);
+    if (st != SIEVE_OK)
+        return st;
+    if (bm)
+        SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
+    SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
+    lane.single = true;
+    lane.busy = true;
+    return SIEVE_OK;
+}
+
 int launch_batch_lane(sieve_server *s, Lane &lane)
 {
     sieve_ctx *c = s->ctx;
@@ -222,6 +250,7 @@ int launch_batch_lane(sieve_server *s, Lane &lane)
                                          hipMemcpyDeviceToHost, lane.stream));
     }
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
+    lane.single = false;
     lane.busy = true;
     return SIEVE_OK;
 }
@@ -244,24 +273,38 @@ int serve_plain(sieve_server *s, Lane &lane, Request *r)
     return SIEVE_OK;
 }
 
+// How long the dispatcher keeps polling after its last activity before it
+// blocks on the submission condition variable.
+constexpr uint64_t kSpinNs = 200000;
+
 void dispatcher(sieve_server *s)
 {
     sieve_ctx *c = s->ctx;
     (void)hipSetDevice(c->device);
     const bool plain = s->cfg.mode == SIEVE_SERVE_PLAIN;
+    uint64_t last_active = now_ns();
     for (;;) {
         bool progressed = false;
         // 1. retire finished lanes
         for (Lane &lane : s->lanes) {
             if (!lane.busy || hipEventQuery(lane.copied) != hipSuccess)
                 continue;
-            lane.eng.pending = false;
-            const unsigned long long *cnt = sv::counts_host(lane.eng);
             std::lock_guard<std::mutex> g(s->m);
-            for (size_t i = 0; i < lane.reqs.size(); ++i) {
-                Request *r = lane.reqs[i];
-                r->pi = cnt[i] + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
+            if (lane.single) {
+                Request *r = lane.reqs[0];
+                const unsigned long long v = *lane.h_pub;
+                if (v == kUnpublished)
+                    r->status = SIEVE_EDEVICE;
+                r->pi = v + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
                 finish_locked(s, r);
+            } else {
+                lane.eng.pending = false;
+                const unsigned long long *cnt = sv::counts_host(lane.eng);
+                for (size_t i = 0; i < lane.reqs.size(); ++i) {
+                    Request *r = lane.reqs[i];
+                    r->pi = cnt[i] + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
+                    finish_locked(s, r);
+                }
             }
             lane.reqs.clear();
             lane.busy = false;
@@ -308,9 +351,15 @@ void dispatcher(sieve_server *s)
                 lane.reqs.clear();
                 s->cv_done.notify_all();
             } else {
-                st = launch_batch_lane(s, lane);
+                st = sv::kNotAsync;
+                if (lane.reqs.size() == 1)
+                    st = launch_single_lane(s, lane);
+                const bool single = st == SIEVE_OK;
+                if (st == sv::kNotAsync)
+                    st = launch_batch_lane(s, lane);
                 std::lock_guard<std::mutex> g(s->m);
                 ++s->stats.batches;
+                s->stats.single_launches += single ? 1 : 0;
                 s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, lane.reqs.size());
                 s->stats.max_inflight = std::max<uint64_t>(s->stats.max_inflight, ++inflight);
                 if (st != SIEVE_OK) {
@@ -326,20 +375,30 @@ void dispatcher(sieve_server *s)
             }
             progressed = true;
         }
-        // 3. sleep when idle
+        // 3. wait.  While a launch is in flight, or requests wait for a lane
+        //    or for budget, or shortly after the last activity, poll again at
+        //    once (yielding the core): a timed sleep costs tens of
+        //    microseconds of timer slack per wake-up, more than a small
+        //    request takes on the device.  Idle for longer: block until a
+        //    submission.
         std::unique_lock<std::mutex> lk(s->m);
         bool busy = false;
         for (Lane &lane : s->lanes)
             busy = busy || lane.busy;
         if (s->stop && !busy && s->pending.empty() && s->admitted.empty())
             return;
+        const uint64_t t = now_ns();
+        if (progressed)
+            last_active = t;
         if (!progressed) {
-            if (busy)  // a batch is running: poll its event again soon
-                s->cv_work.wait_for(lk, std::chrono::microseconds(20));
-            else if (s->pending.empty() && s->admitted.empty() && !s->stop)
+            const bool waiting = !s->pending.empty() || !s->admitted.empty();
+            if (busy || waiting || t - last_active < kSpinNs) {
+                lk.unlock();
+                std::this_thread::yield();
+            } else if (!s->stop) {
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-            else
-                s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+                last_active = now_ns();
+            }
         }
     }
 }
@@ -387,6 +446,13 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
             e = hipEventCreateWithFlags(&lane.copied, hipEventDisableTiming);
         if (e == hipSuccess)
             e = hipMalloc(&lane.d_words, s->cfg.max_batch_words * 4);
+        void *pub = nullptr;
+        if (e == hipSuccess)
+            e = hipHostMalloc(&pub, 64, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) {
+            lane.h_pub = static_cast<volatile unsigned long long *>(pub);
+            e = hipHostGetDevicePointer(reinterpret_cast<void **>(&lane.d_pub), pub, 0);
+        }
         if (e != hipSuccess)
             st = e == hipErrorOutOfMemory ? SIEVE_ENOMEM : SIEVE_EDEVICE;
         if (st == SIEVE_OK)
@@ -520,6 +586,8 @@ int sieve_server_destroy(sieve_server *s)
             sv::engine_free(lane.eng);
         if (lane.d_words)
             (void)hipFree(lane.d_words);
+        if (lane.h_pub)
+            (void)hipHostFree(const_cast<unsigned long long *>(lane.h_pub));
         if (lane.copied)
             (void)hipEventDestroy(lane.copied);
         if (lane.stream)

@@ -74,7 +74,8 @@ class sieve_result(ctypes.Structure):
 
 class sieve_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
-                ("batches", ctypes.c_uint64), ("max_batch_seen", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("single_launches", ctypes.c_uint64),
+                ("max_batch_seen", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                 ("peak_admitted_bytes", ctypes.c_uint64)]
 

@@ -80,9 +80,13 @@ def test_plan_tuning_resolution():
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 13))
     assert p["block_threads"] == 256 and p["dense_limit"] == 128
     assert sv.sieve_plan(2, 10**7)["dense_limit"] == 128
-    # hit buckets: automatic once sqrt(hi) reaches 1.5 segments
+    # hit buckets: automatic once sqrt(hi) reaches 1.5 segments on a range of
+    # at least 2^30 odd integers
     assert sv.sieve_plan(10**12, 10**12 + 10**10)["bucket_limit"] == 1 << 19
     assert sv.sieve_plan(10**11, 10**11 + 10**10)["bucket_limit"] == 0
+    assert sv.sieve_plan(10**12, 10**12 + 2**31 - 2)["bucket_limit"] == 0
+    assert sv.sieve_plan(10**12, 10**12 + 2**31)["bucket_limit"] == 1 << 19
+    assert sv.sieve_plan(10**11, 10**11 + 10**6)["bucket_limit"] == 0
     assert sv.sieve_plan(10**12, 10**12 + 10**10, tuning=dict(bucket_limit=0xFFFFFFFF))["bucket_limit"] == 0
 
 

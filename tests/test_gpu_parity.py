@@ -386,7 +386,7 @@ def test_autotune_single_range_and_batch(gpu, oracle_mod, sv_mod):
     (10**12 + 1, 10**12 + 3 * 10**7 + 7, 65536, 131072, 0),
     (10**12, 10**12 + 2 * 10**7, 65536, 65536, 64),      # tiny depth: overflow, retry
     (10**13 - 3, 10**13 + 2 * 10**7, 131072, 0, 0),      # automatic choice
-    (10**15 - 4 * 10**7, 10**15, 0, 0, 0),               # automatic at the top of the domain
+    (10**15 - 2**31, 10**15, 0, 0, 0),                   # automatic at the top of the domain
 ])
 def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth):
     gpu.tuning(seg_bits=seg_bits, bucket_limit=limit, bucket_depth=depth)
@@ -408,6 +408,10 @@ def test_buckets_off_and_on_agree(gpu, sv_mod):
         a = w0.cpu().numpy()
     finally:
         gpu.tuning(bucket_limit=0)
-    assert sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())["bucket_limit"] > 0
-    w1, p1 = gpu.bitmap(lo, hi)
+    gpu.tuning(bucket_limit=1)  # forced: every prime above the segment size
+    try:
+        assert sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())["bucket_limit"] > 0
+        w1, p1 = gpu.bitmap(lo, hi)
+    finally:
+        gpu.tuning(bucket_limit=0)
     assert p0 == p1 and np.array_equal(a, w1.cpu().numpy())

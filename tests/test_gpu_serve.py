@@ -71,6 +71,33 @@ def test_server_mix_equals_alone_and_oracle(sv, alone, oracle_mod):
         assert got[ids[i]]["pi"] == oracle_mod.count(int(lo[i]), int(hi[i]))
 
 
+def test_server_single_requests_take_the_plain_launch(sv, alone, oracle_mod):
+    # requests submitted one at a time form batches of one, which go through
+    # the plain range launch (count published to the lane's pinned word);
+    # bucketed and empty ranges fall back to the batch launch
+    lo, hi, bm = _requests(31, 40)
+    extra = [(10**12 - 10**6, 10**12 + 3 * 10**6, True),
+             (10**12, 10**12, False), (7, 7, True), (0, 3, True)]  # empty ranges: batch path
+    server = sv.Server(0, lanes=2)
+    try:
+        ids, got = [], {}
+        for i in range(len(lo)):
+            ids.append(server.submit(int(lo[i]), int(hi[i]), bool(bm[i])))
+            got.update(_drain(server, 1))
+        _check_against_alone(alone, lo, hi, bm, ids, got)
+        for (a, b, w) in extra:
+            rid = server.submit(a, b, w)
+            r = _drain(server, 1)[rid]
+            assert r["status"] == 0 and r["pi"] == oracle_mod.count(a, b), (a, b)
+            if w and b // 2 - a // 2 > 0:
+                assert np.array_equal(r["words"], oracle_mod.bitmap(a, b)[0]), (a, b)
+        st = server.stats()
+        assert st["single_launches"] >= len(lo) + 2
+        assert st["batches"] >= st["single_launches"] + 2
+    finally:
+        server.close()
+
+
 def test_server_budget_defers_and_stays_exact(sv, alone):
     # bitmaps of 125 KB .. 1 MB against a 1 MiB budget: admission must wait
     rng = np.random.default_rng(5)
