@@ -291,6 +291,12 @@ int build_primes(sieve_ctx *c, uint64_t limit)
         c->h_recip_prefix.assign(c->h_primes.size() + 1, 0.0);
         for (size_t i = 0; i < c->h_primes.size(); ++i)
             c->h_recip_prefix[i + 1] = c->h_recip_prefix[i] + 1.0 / c->h_primes[i];
+        c->h_pi_index.assign((limit >> kPiIndexShift) + 2, 0);
+        for (size_t k = 0, i = 0; k < c->h_pi_index.size(); ++k) {
+            while (i < c->h_primes.size() && (c->h_primes[i] >> kPiIndexShift) < k)
+                ++i;
+            c->h_pi_index[k] = static_cast<uint32_t>(i);
+        }
         c->primes_limit = limit;
     } while (false);
     (void)hipFree(d_boot);
@@ -320,13 +326,24 @@ int ensure_primes(sieve_ctx *c, uint64_t bound)
 }
 
 // Marking primes for sieving with base-prime bound r: (count, dense count).
+// Number of odd primes <= r in the context's table (r <= primes_limit): the
+// coarse index narrows the search to the primes of one 2^8-wide block.
+uint32_t odd_primes_upto(const sieve_ctx *c, uint64_t r)
+{
+    const auto &v = c->h_primes;
+    const uint64_t k = r >> kPiIndexShift;
+    if (k + 1 >= c->h_pi_index.size())
+        return static_cast<uint32_t>(std::upper_bound(v.begin(), v.end(), r) - v.begin());
+    const auto first = v.begin() + c->h_pi_index[k], last = v.begin() + c->h_pi_index[k + 1];
+    return static_cast<uint32_t>(std::upper_bound(first, last, r) - v.begin());
+}
+
 void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32_t *n_mark,
                     uint32_t *n_dense)
 {
-    const auto &v = c->h_primes;
-    const uint32_t n_odd = static_cast<uint32_t>(std::upper_bound(v.begin(), v.end(), r) - v.begin());
+    const uint32_t n_odd = odd_primes_upto(c, r);
     *n_mark = n_odd > sv::kPresievePrimes ? n_odd - sv::kPresievePrimes : 0;
-    const uint32_t nd = static_cast<uint32_t>(std::lower_bound(v.begin(), v.end(), dense_limit) - v.begin());
+    const uint32_t nd = odd_primes_upto(c, dense_limit - 1);
     *n_dense = std::min(*n_mark, nd > sv::kPresievePrimes ? nd - sv::kPresievePrimes : 0u);
 }
 
@@ -659,6 +676,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : default_threads(sw);
     std::vector<std::pair<uint64_t, uint64_t>> spans;
     uint64_t max_bound = 0, items = 0;
+    e.bound.resize(n);
     for (uint32_t i = 0; i < n; ++i) {
         if (iv[i].lo > iv[i].hi)
             return SIEVE_EINVAL;
@@ -673,8 +691,8 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
             if (nw)
                 spans.emplace_back(iv[i].word_offset, iv[i].word_offset + nw);
         }
-        if (iv[i].hi >= 2)
-            max_bound = std::max(max_bound, isqrt_u64(iv[i].hi - 1));
+        e.bound[i] = iv[i].hi >= 2 ? isqrt_u64(iv[i].hi - 1) : 0;
+        max_bound = std::max(max_bound, e.bound[i]);
         items += (nw + sw - 1) / sw;
     }
     std::sort(spans.begin(), spans.end());
@@ -705,33 +723,42 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     std::memset(blob, 0, kBlobIntervalOff);  // header and work queues
     sv::BatchInterval *h_iv = reinterpret_cast<sv::BatchInterval *>(blob + kBlobIntervalOff);
     uint32_t *h_item = reinterpret_cast<uint32_t *>(blob + blob_items_offset(n));
+    // queue order: intervals by power-of-two class of their marking-prime
+    // count, largest first, input order within a class (a two-pass
+    // counting sort, linear in n)
     e.order.resize(n);
     e.nmark.resize(n);
-    e.ndense.resize(n);
+    const uint32_t nd_all = odd_primes_upto(c, dense_limit - 1);
+    const uint32_t n_dense_max = nd_all > sv::kPresievePrimes ? nd_all - sv::kPresievePrimes : 0u;
+    uint32_t first_of[34] = {};
     for (uint32_t i = 0; i < n; ++i) {
-        marking_primes(c, iv[i].hi >= 2 ? isqrt_u64(iv[i].hi - 1) : 0, dense_limit, &e.nmark[i], &e.ndense[i]);
-        e.order[i] = i;
+        const uint32_t n_odd = odd_primes_upto(c, e.bound[i]);
+        e.nmark[i] = n_odd > sv::kPresievePrimes ? n_odd - sv::kPresievePrimes : 0;
+        ++first_of[32 - __builtin_clz(e.nmark[i] + 1)];
     }
-    std::stable_sort(e.order.begin(), e.order.end(),
-                     [&](uint32_t a, uint32_t b) { return e.nmark[a] > e.nmark[b]; });
-    for (uint32_t i = 0; i < n; ++i) {
-        sv::BatchInterval &b = h_iv[i];
+    for (uint32_t k = 33, at = 0; k-- > 0;) {
+        const uint32_t cnt = first_of[k];
+        first_of[k] = at;
+        at += cnt;
+    }
+    for (uint32_t i = 0; i < n; ++i)
+        e.order[first_of[32 - __builtin_clz(e.nmark[i] + 1)]++] = i;
+    uint32_t next = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint32_t i = e.order[j];
         const uint64_t lo = iv[i].lo, hi = iv[i].hi;
+        sv::BatchInterval b;
         b.first_odd = (lo & ~1ull) + 1;
         b.nbits = hi / 2 - lo / 2;
         b.n_words = (b.nbits + 31) / 32;
         b.word_offset = (iv[i].flags & SIEVE_WANT_BITMAP) ? iv[i].word_offset : ~0ull;
         b.n_primes = e.nmark[i];
-        b.n_dense = e.ndense[i];
+        b.n_dense = std::min(e.nmark[i], n_dense_max);
+        b.seg_begin = next;
         b.pad = 0;
-    }
-    uint32_t next = 0;
-    for (uint32_t j = 0; j < n; ++j) {
-        const uint32_t i = e.order[j];
-        const uint32_t segs = static_cast<uint32_t>((h_iv[i].n_words + sw - 1) / sw);
-        h_iv[i].seg_begin = next;
-        for (uint32_t k = 0; k < segs; ++k)
-            h_item[next + k] = i;
+        h_iv[i] = b;
+        const uint32_t segs = static_cast<uint32_t>((b.n_words + sw - 1) / sw);
+        std::fill(h_item + next, h_item + next + segs, i);
         next += segs;
     }
     sv::BatchHeader *h_hdr = reinterpret_cast<sv::BatchHeader *>(blob);

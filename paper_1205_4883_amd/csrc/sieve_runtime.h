@@ -18,6 +18,7 @@ constexpr uint32_t kSegGranuleWords = 128;         // 4096 bits
 constexpr uint32_t kDefaultMaxSegWords = 16384;    // 2^19 bits = 64 KiB of LDS
 constexpr uint64_t kDefaultBudget = 32ull << 30;
 constexpr uint64_t kBucketPoolBytes = 256ull << 20;  // bucket memory per window of segments
+constexpr uint32_t kPiIndexShift = 8;                // block width of the prime-count index
 
 struct DevBuf {
     void *p = nullptr;
@@ -52,7 +53,9 @@ struct BatchEngine {
     DevBuf blob, counts, item_counts;  // blob: header, work queues, interval table, work list
     HostBuf s_blob, s_counts;
     uint64_t blob_used = 0;  // bytes of the staged blob
-    std::vector<uint32_t> order, nmark, ndense;
+    std::vector<uint32_t> order;  // intervals in queue order
+    std::vector<uint32_t> nmark;
+    std::vector<uint64_t> bound;  // isqrt(hi - 1) per interval
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     GraphKey key{};
@@ -79,6 +82,7 @@ struct sieve_ctx {
     uint64_t primes_limit = 0;
     std::vector<uint32_t> h_primes;
     std::vector<double> h_recip_prefix;  // sum of 1/p over h_primes[0, i)
+    std::vector<uint32_t> h_pi_index;     // [k]: primes in h_primes below k << kPiIndexShift
     uint32_t *d_primes = nullptr;
     double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
 
