@@ -80,15 +80,13 @@ __device__ __forceinline__ uint64_t mont_pow(const Mont &m, uint64_t base_m, uin
     return x;
 }
 
-// One Miller-Rabin round: n - 1 = d * 2^s, d odd.  True when base a does not
-// prove n composite.
-__device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a, uint64_t d, int s)
+// One Miller-Rabin round on a base already in Montgomery form (a R mod n,
+// a not divisible by n): n - 1 = d * 2^s, d odd.  True when the base does
+// not prove n composite.
+__device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a_m, uint64_t d, int s)
 {
-    a %= m.n;
-    if (a == 0)
-        return true;
     const uint64_t minus_one = m.n - m.one;  // (n - 1) R mod n
-    uint64_t x = mont_pow(m, to_mont(m, a), d);
+    uint64_t x = mont_pow(m, a_m, d);
     if (x == m.one || x == minus_one)
         return true;
     for (int j = 1; j < s; ++j) {
@@ -99,66 +97,149 @@ __device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a, uint64_t d, 
     return false;
 }
 
-// Deterministic Miller-Rabin for n < 2^64 with the first k primes as bases,
-// k from the published bounds below which those bases admit no strong
-// pseudoprime (Jaeschke 1993; Sorenson and Webster 2015 for 12 bases).
-__device__ bool is_prime_u64(uint64_t n)
-{
-    constexpr uint32_t kBases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
-    if (n < 2)
-        return false;
-    for (int i = 0; i < 12; ++i) {
-        if (n == kBases[i])
-            return true;
-        if (n % kBases[i] == 0)
-            return false;
-    }
-    if (n < 41 * 41)  // no factor up to 37 and below 41^2: prime
-        return true;
-    int k;
-    if (n < 2047ull)
-        k = 1;
-    else if (n < 1373653ull)
-        k = 2;
-    else if (n < 25326001ull)
-        k = 3;
-    else if (n < 3215031751ull)
-        k = 4;
-    else if (n < 2152302898747ull)
-        k = 5;
-    else if (n < 3474749660383ull)
-        k = 6;
-    else if (n < 341550071728321ull)
-        k = 7;
-    else if (n < 3825123056546413051ull)
-        k = 9;
-    else
-        k = 12;
-    uint64_t d = n - 1;
-    int s = 0;
-    while ((d & 1) == 0) {
-        d >>= 1;
-        ++s;
-    }
-    const Mont m = mont_setup(n);
-    for (int i = 0; i < k; ++i)
-        if (!mr_round(m, kBases[i], d, s))
-            return false;
-    return true;
-}
-
-__global__ void __launch_bounds__(256) mr_kernel(const uint64_t *ns, uint64_t count, uint8_t *out)
-{
-    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < count;
-         i += uint64_t(gridDim.x) * blockDim.x)
-        out[i] = is_prime_u64(ns[i]) ? 1 : 0;
-}
-
 // x + y mod n for x, y < n (the sum may pass 2^64).
 __device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t n)
 {
     const uint64_t s = x + y;
     return (s < x || s >= n) ? s - n : s;
+}
+
+// Deterministic Miller-Rabin for n < 2^64, in three stages so that the
+// expensive rounds run on densely packed lanes (see mr_kernel).  Below
+// 341550071728321 the bases are the first k primes, k from the published
+// bounds below which those bases admit no strong pseudoprime (Jaeschke
+// 1993); above it, the seven bases 2, 325, 9375, 28178, 450775, 9780504,
+// 1795265022, which admit none below 2^64 (Sinclair 2011, checked against
+// the Feitsma-Galway list of base-2 pseudoprimes).
+constexpr uint32_t kSmallBases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+constexpr uint64_t kWideBases[7] = {2, 325, 9375, 28178, 450775, 9780504, 1795265022};
+
+// Rounds needed for n >= 41^2 (the first k small bases, or the 7 wide ones).
+__device__ __forceinline__ int mr_rounds(uint64_t n, bool &wide)
+{
+    wide = false;
+    if (n < 2047ull)
+        return 1;
+    if (n < 1373653ull)
+        return 2;
+    if (n < 25326001ull)
+        return 3;
+    if (n < 3215031751ull)
+        return 4;
+    if (n < 2152302898747ull)
+        return 5;
+    if (n < 3474749660383ull)
+        return 6;
+    if (n < 341550071728321ull)
+        return 7;
+    wide = true;
+    return 7;
+}
+
+// Stage 1: 0 = composite, 1 = prime, 2 = undecided (no factor up to 37,
+// n >= 41^2).
+__device__ __forceinline__ uint32_t mr_stage1(uint64_t n)
+{
+    if (n < 2)
+        return 0;
+    for (int i = 0; i < 12; ++i) {
+        if (n == kSmallBases[i])
+            return 1;
+        if (n % kSmallBases[i] == 0)
+            return 0;
+    }
+    return n < 41 * 41 ? 1 : 2;  // no factor up to 37 and below 41^2: prime
+}
+
+__device__ __forceinline__ void mr_split(uint64_t n, uint64_t &d, int &s)
+{
+    d = n - 1;
+    s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+}
+
+// Stage 2, for an undecided n: the base-2 round, which rejects almost every
+// composite (the Montgomery form of 2 is one modular doubling of R mod n).
+// 0 = composite, 1 = prime (base 2 is all n < 2047 needs), 2 = undecided.
+__device__ __forceinline__ uint32_t mr_stage2(uint64_t n)
+{
+    uint64_t d;
+    int s;
+    mr_split(n, d, s);
+    const Mont m = mont_setup(n);
+    if (!mr_round(m, add_mod(m.one, m.one, n), d, s))
+        return 0;
+    bool wide;
+    return mr_rounds(n, wide) == 1 ? 1 : 2;
+}
+
+// Stage 3: the remaining bases.  Every base is below n here (n >= 41^2 for
+// the small bases, n > 3.4e14 for the wide ones), so none is a multiple of
+// n; each enters Montgomery form through one product with R^2 mod n.
+__device__ __forceinline__ uint32_t mr_stage3(uint64_t n)
+{
+    uint64_t d;
+    int s;
+    mr_split(n, d, s);
+    const Mont m = mont_setup(n);
+    bool wide;
+    const int rounds = mr_rounds(n, wide);
+    const uint64_t r2 = to_mont(m, m.one);  // R^2 mod n
+    for (int i = 1; i < rounds; ++i) {
+        const uint64_t a = wide ? kWideBases[i] : kSmallBases[i];
+        if (!mr_round(m, mont_mul(m, a, r2), d, s))
+            return 0;
+    }
+    return 1;
+}
+
+// One workgroup takes chunks of kMrChunk candidates: every lane runs stage 1
+// on its share and queues the undecided ones in LDS; the queue is then
+// worked off densely by stage 2, whose survivors (mostly primes) form a
+// second queue for stage 3.  Without the queues nearly every wave would
+// carry a prime through all its rounds with most lanes idle.
+constexpr uint32_t kMrThreads = 256;
+constexpr uint32_t kMrChunk = 4096;
+
+__global__ void __launch_bounds__(kMrThreads) mr_kernel(const uint64_t *ns, uint64_t count, uint8_t *out)
+{
+    __shared__ uint32_t q1[kMrChunk], q2[kMrChunk];
+    __shared__ uint32_t n1, n2;
+    const uint32_t t = threadIdx.x;
+    for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kMrChunk; base < count;
+         base += static_cast<uint64_t>(gridDim.x) * kMrChunk) {
+        if (t == 0) {
+            n1 = 0;
+            n2 = 0;
+        }
+        __syncthreads();
+        const uint32_t here = static_cast<uint32_t>(count - base < kMrChunk ? count - base : kMrChunk);
+        for (uint32_t j = t; j < here; j += kMrThreads) {
+            const uint32_t v = mr_stage1(ns[base + j]);
+            if (v == 2)
+                q1[atomicAdd(&n1, 1u)] = j;
+            else
+                out[base + j] = static_cast<uint8_t>(v);
+        }
+        __syncthreads();
+        for (uint32_t e = t; e < n1; e += kMrThreads) {
+            const uint32_t j = q1[e];
+            const uint32_t v = mr_stage2(ns[base + j]);
+            if (v == 2)
+                q2[atomicAdd(&n2, 1u)] = j;
+            else
+                out[base + j] = static_cast<uint8_t>(v);
+        }
+        __syncthreads();
+        for (uint32_t e = t; e < n2; e += kMrThreads) {
+            const uint32_t j = q2[e];
+            out[base + j] = static_cast<uint8_t>(mr_stage3(ns[base + j]));
+        }
+        __syncthreads();  // the queues are reused by the next chunk
+    }
 }
 
 // a * b mod n for any n > 1 by doubling and adding (64 steps).
@@ -203,9 +284,10 @@ __global__ void __launch_bounds__(256) fermat_kernel(const uint64_t *ns, uint64_
             }
         } else {
             const Mont m = mont_setup(n);
+            const uint64_t r2 = to_mont(m, m.one);  // R^2 mod n
             for (uint32_t j = 0; j < iterations && pass; ++j) {
-                const uint64_t a = draws[j] % (n - 1) + 1;
-                pass = mont_pow(m, to_mont(m, a), n - 1) == m.one ? 1 : 0;
+                const uint64_t a = draws[j] % (n - 1) + 1;  // a < n
+                pass = mont_pow(m, mont_mul(m, a, r2), n - 1) == m.one ? 1 : 0;
             }
         }
         out[i] = pass;
@@ -218,7 +300,7 @@ hipError_t launch_is_prime(const uint64_t *d_n, uint64_t count, uint8_t *d_out, 
 {
     if (count == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(mr_kernel, dim3(blocks), dim3(256), 0, s, d_n, count, d_out);
+    hipLaunchKernelGGL(mr_kernel, dim3(blocks), dim3(kMrThreads), 0, s, d_n, count, d_out);
     return hipGetLastError();
 }
 
@@ -243,8 +325,8 @@ int sieve_is_prime_batch(sieve_ctx *c, const uint64_t *d_n, uint64_t count, uint
         return SIEVE_OK;
     SV_HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
-    const uint64_t want = (count + 255) / 256;
-    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 64ull * c->n_cu));
+    const uint64_t want = (count + sv::kMrChunk - 1) / sv::kMrChunk;  // one chunk per workgroup pass
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 16ull * c->n_cu));
     c->ev_valid = false;
     SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
     SV_HIP_TRY(c, sv::launch_is_prime(d_n, count, d_out, blocks, s));
