@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--serve-rates", default="20000,100000",
                     help="c5 only: extra arrival rates (req/s) replayed for 2 s each, both modes")
     ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched-vs-plain comparison in the default line")
+                    help="skip the batch, serving and Miller-Rabin blocks of the default line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true",
                     help="c4: skip the 4096 one-at-a-time calls (e.g. under a profiler)")
@@ -381,6 +381,7 @@ def main():
     s.close()
     if args.workload == "c3" and not args.no_batch:
         rec["serve"] = run_serve(sv, args.serve_seconds or 5.0, modes=("batched",))
+        rec["mr"] = run_mr(sv, torch, steps=3, warmup=1)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"])
     print(json.dumps(rec), flush=True)

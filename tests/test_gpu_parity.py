@@ -267,6 +267,21 @@ def test_batch_matches_oracle(gpu, oracle_mod):
     assert np.array_equal(pi, pi2)
 
 
+def test_batch_near_the_top_of_the_domain(gpu, oracle_mod):
+    # intervals up to SIEVE_MAX_HI need base primes up to 31,622,776 (the
+    # batch kernel scans them all per segment, no buckets)
+    los = np.array([10**15 - 3 * 10**6, 10**15 - 10**5 - 1, 9 * 10**14 + 7, 10**15 - 64], dtype=np.uint64)
+    his = np.array([10**15, 10**15 - 10**5 + 12345, 9 * 10**14 + 2 * 10**6, 10**15], dtype=np.uint64)
+    print("case batch near 1e15", flush=True)
+    pi, words, offs = gpu.batch(los, his, want_bitmap=True)
+    host = words.cpu().numpy().view(np.uint32)
+    for i in range(len(los)):
+        ref, ref_pi = oracle_mod.bitmap(int(los[i]), int(his[i]))
+        assert int(pi[i]) == ref_pi, i
+        o = int(offs[i])
+        assert np.array_equal(host[o:o + ref.size], ref), i
+
+
 def test_async_bitmaps_on_several_streams(gpu, oracle_mod, sv_mod):
     # asynchronous calls on different streams overlap on the device; each must
     # keep its own segment queue

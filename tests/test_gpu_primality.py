@@ -51,6 +51,28 @@ def test_equals_sieve_bitmap_near_1e12_and_1e15(gpu):
         assert not gpu.is_prime(evens).any()
 
 
+def test_queues_full_of_primes_and_of_pseudoprime_candidates(gpu, oracle_mod):
+    # the kernel queues undecided candidates in LDS per chunk of 4096: a batch
+    # of nothing but primes fills both queues, a batch of odd composites with
+    # no factor up to 37 fills the first; ragged lengths leave partial chunks
+    words, _ = oracle_mod.bitmap(10**15 - 6 * 10**5, 10**15)
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little")[: (6 * 10**5) // 2].astype(bool)
+    odd = (10**15 - 6 * 10**5 + 1) + 2 * np.arange(bits.size, dtype=np.uint64)
+    primes = odd[bits]
+    assert primes.size > 4096 * 3
+    for n in [primes.size, 4096 * 3 + 17, 4095, 1]:
+        assert gpu.is_prime(primes[:n]).all()
+    small = np.array([3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37], dtype=np.uint64)
+    rough = odd[~bits]
+    rough = rough[np.all(rough[:, None] % small[None, :] != 0, axis=1)]
+    assert rough.size > 4096 * 2
+    assert not gpu.is_prime(rough).any()
+    mixed = np.concatenate([rough[:5000], primes[:5000]])
+    np.random.default_rng(5).shuffle(mixed)
+    got = gpu.is_prime(mixed)
+    assert np.array_equal(got, np.isin(mixed, primes[:5000]))
+
+
 def test_random_u64_equal_oracle_mr(gpu, oracle_mod):
     rng = np.random.default_rng(17)
     ns = rng.integers(0, 2**63, 40000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
