@@ -591,7 +591,7 @@ int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
                                     static_cast<const double *>(k.inv), k.words,
                                     static_cast<uint32_t *>(const_cast<void *>(k.item_counts)),
                                     static_cast<unsigned long long *>(const_cast<void *>(k.counts)),
-                                    k.seg_words, k.threads, k.blocks, cs);
+                                    k.seg_words, k.threads, k.blocks, k.small, cs);
     if (e == hipSuccess)
         e = hipMemcpyAsync(const_cast<void *>(k.h_counts), k.counts, k.counts_bytes,
                            hipMemcpyDeviceToHost, cs);
@@ -774,6 +774,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     e.seg_words = sw;
     e.dense_limit = dense_limit;
     e.threads = threads;
+    e.small = max_bound < (1ull << 24);
     return SIEVE_OK;
 }
 
@@ -798,6 +799,7 @@ int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s
     k.blocks = per_cu * c->n_cu;
     k.max_intervals = static_cast<uint32_t>(e.counts.bytes / sizeof(unsigned long long));
     k.counts_bytes = e.counts.bytes;
+    k.small = e.small;
     if (!e.exec || !(e.key == k))
         if (int st = capture_batch_graph(c, e, k))
             return st;

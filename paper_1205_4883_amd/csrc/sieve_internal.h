@@ -131,10 +131,11 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
 // item's count into item_counts[item]) and the reduction kernel (counts[k] =
 // the sum over interval k's items); all three read their sizes and the table
 // offsets from the blob's header.  max_intervals sizes the reduction grid.
+// small: every marking prime of the batch is below 2^24 (24-bit products).
 hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
                         const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
                         unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
-                        uint32_t n_blocks, hipStream_t s);
+                        uint32_t n_blocks, bool small, hipStream_t s);
 
 // The segment kernels are built for a few static LDS sizes: the smallest
 // capacity (in words) that holds seg_words (0 if none), the LDS bytes a

@@ -200,7 +200,7 @@ __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t 
     const uint32_t c = 15 * (lane >> 3) + e;
     const uint32_t c63 = 105 + 15 - ((g >> 14) & 3);  // the eight gaps sum to 15
     const uint32_t q = 120 * p;                       // bits between a lane's classes
-    const uint32_t x0 = o + c * p;
+    const uint32_t x0 = o + __umul24(c, p);           // dense primes are below 2^20
     const uint32_t x1 = x0 + q, x2 = x1 + q, x3 = x2 + q;
     uint32_t *p0 = seg + (x0 >> 5);
     uint32_t *p1 = seg + (x1 >> 5);
@@ -237,16 +237,21 @@ __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t 
 // Returns the offset of the first multiple left unmarked (at or past
 // lim_bits) and sets idx to its wheel position, so that the next segment
 // can continue from there.
+// kSmall: p < 2^24, so the offsets are full-rate 24-bit products.
+template <bool kSmall>
 __device__ __forceinline__ uint32_t mark_wheel(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
                                                uint32_t &idx)
 {
     const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
     uint32_t d[8];
     d[0] = 0;
+    uint32_t cum = 0;  // odd steps from the turn's first multiple
 #pragma unroll
-    for (int j = 1; j < 8; ++j)
-        d[j] = d[j - 1] + ((g >> (2 * (j - 1))) & 3u) * p;
-    const uint32_t turn = 15 * p;
+    for (int j = 1; j < 8; ++j) {
+        cum += (g >> (2 * (j - 1))) & 3u;
+        d[j] = kSmall ? __umul24(cum, p) : cum * p;
+    }
+    const uint32_t turn = kSmall ? __umul24(15u, p) : 15 * p;
     uint32_t base = o;
     for (; base + d[7] < lim_bits; base += turn) {
 #pragma unroll
@@ -421,6 +426,7 @@ __device__ __forceinline__ void seg_dense(uint32_t *seg_lds, const SegGeom &g, c
 
 // 2b. sparse primes [i_begin, n_primes): one lane per prime, each start
 //     computed afresh for this segment.
+template <bool kSmall>
 __device__ __forceinline__ void seg_sparse(uint32_t *seg_lds, const SegGeom &g, const uint32_t *primes,
                                            const double *inv, uint32_t i_begin, uint32_t n_primes)
 {
@@ -429,8 +435,14 @@ __device__ __forceinline__ void seg_sparse(uint32_t *seg_lds, const SegGeom &g, 
         const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
         uint32_t o = st.off;
         uint32_t idx = wheel_start(p, o, st.m30);
-        (void)mark_wheel(seg_lds, g.lim_bits, p, o, idx);
+        (void)mark_wheel<kSmall>(seg_lds, g.lim_bits, p, o, idx);
     }
+}
+
+// Whether every marking prime is below 2^24 (the largest is the last).
+__device__ __forceinline__ bool small_primes(const uint32_t *primes, uint32_t n_primes)
+{
+    return n_primes == 0 || primes[n_primes - 1] < (1u << 24);
 }
 
 // 2c. large primes: the segment's bucket of precomputed hits.
@@ -512,8 +524,8 @@ __device__ void finish_launch(const RangeArgs &r, unsigned long long wg_count)
 // Sieve segment `seg` of one range into LDS and emit its words; returns the
 // number of primes among this thread's words.  tabs: the pre-sieve tables in
 // LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
-// its next __syncthreads.
-template <bool kWrite>
+// its next __syncthreads.  kSmall: every marking prime is below 2^24.
+template <bool kWrite, bool kSmall>
 __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
                                   uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
                                   const uint32_t *primes, const double *inv, uint32_t n_dense,
@@ -523,7 +535,7 @@ __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint3
     seg_presieve(tabs, seg_lds, g);
     __syncthreads();
     seg_dense(seg_lds, g, primes, inv, n_dense);
-    seg_sparse(seg_lds, g, primes, inv, n_dense, n_primes);
+    seg_sparse<kSmall>(seg_lds, g, primes, inv, n_dense, n_primes);
     __syncthreads();
     return seg_count<kWrite>(seg_lds, g, first_odd, nbits, n_words, out);
 }
@@ -534,6 +546,38 @@ __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint3
 constexpr int kCarry = 4;
 constexpr uint32_t kCarryCap = 1u << 28;
 constexpr uint32_t kCarryNone = 0xffffffffu;
+
+// The sparse primes of one segment of a run: the first kCarry per lane
+// continue from the multiple carried over from the previous segment (or
+// start afresh on the run's first segment, k == 0), the rest start afresh.
+template <bool kSmall>
+__device__ __forceinline__ void sparse_phase(uint32_t *seg, const SegGeom &g, const PrimeArgs &pa, uint32_t t,
+                                             uint32_t k, uint32_t carry_end, uint32_t (&carry)[kCarry])
+{
+#pragma unroll
+    for (int j = 0; j < kCarry; ++j) {
+        const uint32_t i = pa.n_dense + t + j * blockDim.x;
+        if (i >= carry_end)
+            break;
+        const uint32_t p = pa.primes[i];
+        uint32_t o, idx;
+        if (k == 0 || carry[j] == kCarryNone) {
+            const Start st = first_multiple(g.n0, g.nf, p, pa.inv[i], kCarryCap);
+            o = st.off;
+            if (o >= kCarryCap) {  // p*p lies far ahead: look again next segment
+                carry[j] = kCarryNone;
+                continue;
+            }
+            idx = wheel_start(p, o, st.m30);
+        } else {
+            o = carry[j] & (kCarryCap - 1);
+            idx = carry[j] >> 29;
+        }
+        o = mark_wheel<kSmall>(seg, g.lim_bits, p, o, idx) - g.lim_bits;
+        carry[j] = o < kCarryCap ? (idx << 29) | o : kCarryNone;
+    }
+    seg_sparse<kSmall>(seg, g, pa.primes, pa.inv, carry_end, pa.n_primes);
+}
 
 // Resident workgroups pop work items from the launch's work queues (zero at
 // launch) until every item is taken, so the grid size need not match the
@@ -559,6 +603,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     const uint32_t t = threadIdx.x;
     const uint32_t n_items = n_chunks + (n_segments - n_chunks * chunk);
     const uint32_t carry_end = min(pa.n_primes, pa.n_dense + kCarry * blockDim.x);
+    const bool small = small_primes(pa.primes, pa.n_primes);
     uint32_t q = blockIdx.x % kQueues, dry = 0;
     unsigned long long acc = 0;
     uint32_t carry[kCarry];
@@ -580,29 +625,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             seg_presieve(tabs, seg, g);
             __syncthreads();
             seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense);
-#pragma unroll
-            for (int j = 0; j < kCarry; ++j) {
-                const uint32_t i = pa.n_dense + t + j * blockDim.x;
-                if (i >= carry_end)
-                    break;
-                const uint32_t p = pa.primes[i];
-                uint32_t o, idx;
-                if (k == 0 || carry[j] == kCarryNone) {
-                    const Start st = first_multiple(g.n0, g.nf, p, pa.inv[i], kCarryCap);
-                    o = st.off;
-                    if (o >= kCarryCap) {  // p*p lies far ahead: look again next segment
-                        carry[j] = kCarryNone;
-                        continue;
-                    }
-                    idx = wheel_start(p, o, st.m30);
-                } else {
-                    o = carry[j] & (kCarryCap - 1);
-                    idx = carry[j] >> 29;
-                }
-                o = mark_wheel(seg, g.lim_bits, p, o, idx) - g.lim_bits;
-                carry[j] = o < kCarryCap ? (idx << 29) | o : kCarryNone;
-            }
-            seg_sparse(seg, g, pa.primes, pa.inv, carry_end, pa.n_primes);
+            if (small)
+                sparse_phase<true>(seg, g, pa, t, k, carry_end, carry);
+            else
+                sparse_phase<false>(seg, g, pa, t, k, carry_end, carry);
             if (r.buckets)
                 seg_buckets(seg, first + k, r.buckets, r.bucket_count, r.bucket_depth);
             __syncthreads();
@@ -620,7 +646,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 // item's count goes to item_counts[item] with a plain store (thread 0, at
 // the next pop).  All sizes are read from device memory, so one captured
 // graph serves batches of any size up to its buffers' capacity.
-template <uint32_t kSegMax>
+template <uint32_t kSegMax, bool kSmall>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) batch_kernel(
     BatchHeader *hdr, const uint32_t *primes, const double *inv, uint32_t *words,
     uint32_t *item_counts, uint32_t seg_words)
@@ -658,10 +684,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         const uint64_t s = item - iv.seg_begin;
         uint32_t c;
         if (iv.word_offset != ~0ull)
-            c = sieve_segment<true>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
+            c = sieve_segment<true, kSmall>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
                                     iv.n_dense, iv.n_primes, words + iv.word_offset);
         else
-            c = sieve_segment<false>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
+            c = sieve_segment<false, kSmall>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
                                      iv.n_dense, iv.n_primes, nullptr);
         c = wave_sum(c);
         if ((threadIdx.x & 63) == 0)
@@ -980,10 +1006,14 @@ void launch_range_cap(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_words
 template <uint32_t kSegMax>
 void launch_batch_cap(BatchHeader *d_blob, const uint32_t *d_primes, const double *d_inv,
                       uint32_t *d_words, uint32_t *d_item_counts, uint32_t seg_words, uint32_t threads,
-                      uint32_t grid, hipStream_t s)
+                      uint32_t grid, bool small, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_kernel<kSegMax>), dim3(grid), dim3(threads), 0, s, d_blob, d_primes, d_inv,
-                       d_words, d_item_counts, seg_words);
+    if (small)
+        hipLaunchKernelGGL((batch_kernel<kSegMax, true>), dim3(grid), dim3(threads), 0, s, d_blob, d_primes, d_inv,
+                           d_words, d_item_counts, seg_words);
+    else
+        hipLaunchKernelGGL((batch_kernel<kSegMax, false>), dim3(grid), dim3(threads), 0, s, d_blob, d_primes, d_inv,
+                           d_words, d_item_counts, seg_words);
 }
 }  // namespace
 
@@ -1048,11 +1078,11 @@ uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
 {
     const uint32_t cap = seg_capacity_for(seg_words);
     switch (cap) {
-    case 512: return blocks_per_cu(batch_kernel<512>, threads, 2, cap);
-    case 2048: return blocks_per_cu(batch_kernel<2048>, threads, 2, cap);
-    case 8192: return blocks_per_cu(batch_kernel<8192>, threads, 2, cap);
-    case 16384: return blocks_per_cu(batch_kernel<16384>, threads, 2, cap);
-    case 32768: return blocks_per_cu(batch_kernel<32768>, threads, 2, cap);
+    case 512: return blocks_per_cu(batch_kernel<512, true>, threads, 2, cap);
+    case 2048: return blocks_per_cu(batch_kernel<2048, true>, threads, 2, cap);
+    case 8192: return blocks_per_cu(batch_kernel<8192, true>, threads, 2, cap);
+    case 16384: return blocks_per_cu(batch_kernel<16384, true>, threads, 2, cap);
+    case 32768: return blocks_per_cu(batch_kernel<32768, true>, threads, 2, cap);
     default: return 1;
     }
 }
@@ -1115,17 +1145,17 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
 hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
                         const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
                         unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
-                        uint32_t n_blocks, hipStream_t s)
+                        uint32_t n_blocks, bool small, hipStream_t s)
 {
     if (n_blocks == 0)
         return hipSuccess;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, d_blob);
     switch (seg_capacity_for(seg_words)) {
-    case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
-    case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
-    case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
-    case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
-    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, s); break;
+    case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
+    case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
+    case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
+    case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
+    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
     default: return hipErrorInvalidValue;
     }
     const uint32_t waves_blocks = (max_intervals + 3) / 4;  // four wavefronts per block

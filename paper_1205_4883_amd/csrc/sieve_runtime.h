@@ -36,12 +36,13 @@ struct GraphKey {
     uint32_t *words;
     uint32_t seg_words, threads, blocks, max_intervals;
     size_t counts_bytes;
+    bool small;  // every marking prime below 2^24
     bool operator==(const GraphKey &o) const
     {
         return blob == o.blob && counts == o.counts && item_counts == o.item_counts && h_counts == o.h_counts &&
                primes == o.primes && inv == o.inv && words == o.words && seg_words == o.seg_words &&
                threads == o.threads && blocks == o.blocks && max_intervals == o.max_intervals &&
-               counts_bytes == o.counts_bytes;
+               counts_bytes == o.counts_bytes && small == o.small;
     }
 };
 
@@ -64,6 +65,7 @@ struct BatchEngine {
     uint32_t n = 0;             // intervals staged
     uint64_t items = 0;         // work items staged
     uint32_t seg_words = 0, dense_limit = 0, threads = 0;
+    bool small = true;  // every marking prime of the staged batch below 2^24
 };
 
 }  // namespace sv
