@@ -113,8 +113,9 @@ typedef struct sieve_plan_info {
  * released with sieve_destroy. */
 SIEVE_API int sieve_create(sieve_ctx **ctx, int hip_device, uint64_t hbm_budget_bytes);
 
-/* Release a context and everything it owns.  Waits for its stream.
- * NULL is accepted and ignored. */
+/* Release a context and everything it owns.  Waits for its stream and for
+ * its asynchronous calls still running on other streams.  NULL is accepted
+ * and ignored. */
 SIEVE_API int sieve_destroy(sieve_ctx *ctx);
 
 /* Static English text for a status code (never NULL). */

@@ -916,6 +916,11 @@ int sieve_destroy(sieve_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
+    // asynchronous calls on the caller's streams may still read the prime
+    // table, their counter slot and the bucket pool
+    for (int i = 0; i < sieve_ctx::kSlots; ++i)
+        if (c->slot_used[i] && c->slot_done[i])
+            (void)hipEventSynchronize(c->slot_done[i]);
     sv::engine_free(c->batch);
     for (sv::DevBuf *b : {&c->b_buckets, &c->b_bcount})
         if (b->p)

@@ -466,14 +466,17 @@ __device__ __forceinline__ uint32_t seg_count(uint32_t *seg_lds, const SegGeom &
                                               uint64_t nbits, uint64_t n_words, uint32_t *out)
 {
     const uint32_t t = threadIdx.x;
-    if (t == 0) {
-        if (g.w0 == 0)
-            seg_lds[0] = ~fix_first_word(~seg_lds[0], first_odd);
-        const uint32_t tail = static_cast<uint32_t>(nbits & 31);
-        if (tail && g.w0 + g.sw == n_words)
-            seg_lds[g.sw - 1] |= ~((1u << tail) - 1);
+    const uint32_t tail = static_cast<uint32_t>(nbits & 31);
+    const bool first = g.w0 == 0, last = tail && g.w0 + g.sw == n_words;
+    if (first || last) {  // uniform over the workgroup
+        if (t == 0) {
+            if (first)
+                seg_lds[0] = ~fix_first_word(~seg_lds[0], first_odd);
+            if (last)
+                seg_lds[g.sw - 1] |= ~((1u << tail) - 1);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     uint32_t c = 0;
     uint32_t *o = kWrite ? out + g.w0 : nullptr;
     for (uint32_t w = t; w < g.sw; w += blockDim.x) {
