@@ -2,16 +2,23 @@
 
 Default workload: the count-only sieve of [2, 1e10) (pi = 455052511), one
 step = one sieve_range_count call (base primes resident, pre-sieve, dense and
-sparse marking, popcount reduction, 8-byte readback).  Prints one JSON line.
+sparse marking, popcount reduction, count published to pinned memory).
+Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Workloads: count-1e10 (default), bitmap-1e9, bitmap-1e7 (one range per
+step), batch-4096 (4096 seeded intervals per sieve_batch call), serve-2000
+(a 60 s Poisson trace through the serving loop), mr-2e24 (Miller-Rabin of
+2^24 random odd 64-bit integers).
 
 Throughput is sieved integers per second, (hi - lo) / step time.  The roofline
 object prices the marking kernel's algorithmic LDS work (one 32-bit LDS
 atomic per crossed-off odd multiple of every base prime 7 <= p <= sqrt(hi-1),
 plus one LDS write and one read per bitmap word) against the chip's LDS
-lane-op peak; see the design doc for the derivation.  The cpu_baseline object
-times the CPU oracle on the host over the same range.
+lane-op peak: 256 CUs x 32 banks x 2.4 GHz, one 32-bit access per bank per
+clock.  The cpu_baseline object times the CPU oracle on the host over the
+same range.
 """
 import argparse
 import hashlib
@@ -27,11 +34,11 @@ if ROOT not in sys.path:
 METRIC = "sieved ints/s on [2,1e10] (% roofline); batched vs plain speedup; p50/p99 ms"
 
 WORKLOADS = {
-    "c1": dict(lo=2, hi=10**7, bitmap=True, pi=664579,
+    "bitmap-1e7": dict(lo=2, hi=10**7, bitmap=True, pi=664579,
                name="plain sieve of [2, 1e7): odd-only bitmap to HBM plus pi"),
-    "c2": dict(lo=2, hi=10**9, bitmap=True, pi=50847534,
+    "bitmap-1e9": dict(lo=2, hi=10**9, bitmap=True, pi=50847534,
                name="plain sieve of [2, 1e9): odd-only bitmap (62.5 MB) to HBM plus pi"),
-    "c3": dict(lo=2, hi=10**10, bitmap=False, pi=455052511,
+    "count-1e10": dict(lo=2, hi=10**10, bitmap=False, pi=455052511,
                name="count-only segmented sieve of [2, 1e10)"),
 }
 
@@ -149,7 +156,7 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
     rec["roofline"] = {
         "bound": "lds", "achieved": lane_ops / (g_ms * 1e-3) / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
         "unit": "Glane-op/s", "frac": lane_ops / (g_ms * 1e-3) / LDS_PEAK_LANE_OPS,
-        "traffic": load_traffic("c4"), "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms,
+        "traffic": load_traffic("batch-4096"), "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms,
         "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": total}}
     if check_plain:
         # the same outputs, one plain call per interval (pi returned per call)
@@ -261,16 +268,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "mr"])
+    ap.add_argument("--workload", default="count-1e10",
+                    choices=sorted(WORKLOADS) + ["batch-4096", "serve-2000", "mr-2e24"])
     ap.add_argument("--serve-seconds", type=float, default=None,
-                    help="trace length for the served workload (c5: 60, default line: 5)")
+                    help="trace length for the served workload (serve-2000: 60, default line: 5)")
     ap.add_argument("--serve-rates", default="20000,100000",
-                    help="c5 only: extra arrival rates (req/s) replayed for 2 s each, both modes")
+                    help="serve-2000 only: extra arrival rates (req/s) replayed for 2 s each, both modes")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch, serving and Miller-Rabin blocks of the default line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true",
-                    help="c4: skip the 4096 one-at-a-time calls (e.g. under a profiler)")
+                    help="batch-4096: skip the 4096 one-at-a-time calls (e.g. under a profiler)")
     ap.add_argument("--seg-bits", type=int, default=0, help="tuning: odd integers per segment")
     ap.add_argument("--dense-limit", type=int, default=0, help="tuning: wave-per-prime bound")
     ap.add_argument("--block-threads", type=int, default=0, help="tuning: threads per workgroup")
@@ -280,7 +288,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "split of a range is described in DESIGN.md but not built.", file=sys.stderr)
+              "split of a range (shards of ceil(n/G) integers, one 8-byte sum) is designed but not "
+              "built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -298,7 +307,7 @@ def main():
 
     import paper_1205_4883_amd as sv
 
-    if args.workload == "mr":
+    if args.workload == "mr-2e24":
         r = run_mr(sv, torch, args.steps, args.warmup)
         print(json.dumps({
             "metric": "Miller-Rabin candidates/s (64-bit)", "value": r["candidates_per_s"],
@@ -308,7 +317,7 @@ def main():
             "config": {"workload": r["workload"]}, "mr": r}), flush=True)
         return
 
-    if args.workload == "c5":
+    if args.workload == "serve-2000":
         secs = args.serve_seconds or 60.0
         r = run_serve(sv, secs)
         r["load_sweep"] = [run_serve(sv, 2.0, rate=float(x)) for x in args.serve_rates.split(",") if x]
@@ -319,7 +328,7 @@ def main():
             "config": {"workload": r["workload"]}, "serve": r}), flush=True)
         return
 
-    if args.workload == "c4":
+    if args.workload == "batch-4096":
         s = sv.Sieve(0)
         if args.seg_bits or args.dense_limit or args.block_threads:
             s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
@@ -404,10 +413,10 @@ def main():
                    "block_threads": plan["block_threads"], "n_segments": plan["n_segments"]},
         "roofline": roof,
     }
-    if args.workload == "c3" and not args.no_batch:
+    if args.workload == "count-1e10" and not args.no_batch:
         rec["batch"] = run_batch(sv, torch, s, steps=3, warmup=1)
     s.close()
-    if args.workload == "c3" and not args.no_batch:
+    if args.workload == "count-1e10" and not args.no_batch:
         rec["serve"] = run_serve(sv, args.serve_seconds or 5.0, modes=("batched",))
         rec["mr"] = run_mr(sv, torch, steps=3, warmup=1)
     if not args.no_cpu:
