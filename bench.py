@@ -50,22 +50,12 @@ HBM_PEAK_BPS = 8.0e12
 
 
 def device_info(torch):
-    """Name and compute units from the runtime, and the current shader clock
-    from rocm-smi when it answers within a few seconds."""
-    import subprocess
-
+    """Name, architecture and compute-unit count as the runtime reports them.
+    No helper program is started: under a profiler every child process would
+    inherit its preloaded library."""
     props = torch.cuda.get_device_properties(0)
-    info = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+    return {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
             "compute_units": props.multi_processor_count}
-    try:
-        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=10).stdout
-        for line in out.splitlines():
-            if "sclk" in line and "Mhz" in line:
-                info["sclk"] = line.split(":", 1)[-1].strip()
-                break
-    except (OSError, subprocess.SubprocessError):
-        pass
-    return info
 
 
 def algorithmic_lds_ops(primes, lo, hi):
