@@ -13,12 +13,14 @@ step), batch-4096 (4096 seeded intervals per sieve_batch call), serve-2000
 2^24 random odd 64-bit integers).
 
 Throughput is sieved integers per second, (hi - lo) / step time.  The roofline
-object prices the marking kernel's algorithmic LDS work (one 32-bit LDS
-atomic per crossed-off odd multiple of every base prime 7 <= p <= sqrt(hi-1),
-plus one LDS write and one read per bitmap word) against the chip's LDS
-lane-op peak: 256 CUs x 32 banks x 2.4 GHz, one 32-bit access per bank per
-clock.  The cpu_baseline object times the CPU oracle on the host over the
-same range.
+object prices the marking kernel's algorithmic LDS work against the chip's LDS
+lane-op peak (256 CUs x 32 banks x 2.4 GHz, one 32-bit access per bank per
+clock).  The work is one 32-bit LDS atomic per crossed-off odd multiple m of
+every base prime 37 <= p <= sqrt(hi-1), max(p^2, lo) <= m < hi (the kernels
+strike 3..31 with periodic pre-sieve tables), plus one LDS write and one read
+per bitmap word; frac_wheel30 prices the larger wheel-30 work (marks from
+p = 7) for comparison.  The cpu_baseline object times the CPU oracle on the
+host over the same range.
 """
 import argparse
 import hashlib
@@ -49,29 +51,114 @@ LDS_PEAK_LANE_OPS = N_CU * CLOCK_HZ * LDS_LANES_PER_CLK
 HBM_PEAK_BPS = 8.0e12
 
 
+def _active_level(path):
+    """The line marked '*' (the current level) of an amdgpu pp_dpm_* file."""
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.rstrip().endswith("*"):
+                    return line.split(":", 1)[-1].strip(" *\n")
+    except OSError:
+        pass
+    return None
+
+
 def device_info(torch):
-    """Name, architecture and compute-unit count as the runtime reports them.
-    No helper program is started: under a profiler every child process would
-    inherit its preloaded library."""
+    """Name, architecture and compute-unit count as the runtime reports them,
+    and the current shader and memory clock levels read from the device's PCI
+    sysfs node (no helper program is started: under a profiler every child
+    process would inherit its preloaded library)."""
     props = torch.cuda.get_device_properties(0)
-    return {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+    info = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
             "compute_units": props.multi_processor_count}
+    try:
+        node = "/sys/bus/pci/devices/%04x:%02x:%02x.0" % (
+            props.pci_domain_id, props.pci_bus_id, props.pci_device_id)
+    except AttributeError:
+        return info
+    for key, fname in (("sclk", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk")):
+        level = _active_level(os.path.join(node, fname))
+        if level:
+            info[key] = level
+    return info
 
 
-def algorithmic_lds_ops(primes, lo, hi):
-    """Marks (odd multiples m of each base prime 7 <= p <= isqrt(hi-1) with
-    max(p^2, lo) <= m < hi) plus two LDS accesses per bitmap word."""
+def host_info(threads):
+    """Host CPU model, logical CPUs visible to this process, oracle threads."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "threads": threads}
+
+
+# Odd primes the segment kernels strike with periodic pre-sieve tables instead
+# of marking; crossing off starts at the next prime.
+PRESIEVE_PRIMES = [3, 5, 7, 11, 13, 17, 19, 23, 29, 31]
+FIRST_MARKED_PRIME = 37
+
+
+def _odd_multiples(p, lo, hi):
+    """Per prime p: the odd multiples m of p with max(p^2, lo) <= m < hi."""
     import numpy as np
 
-    p = primes[(primes >= 7)].astype(np.int64)
-    p = p[p * p <= hi - 1]
     a = np.maximum(p * p, lo)
     jhi = (hi - 1) // p          # largest multiplier with m < hi
     jlo = -(-a // p)             # smallest multiplier with m >= a
     odd_upto = lambda x: (x + 1) // 2  # odd j in [1, x]
-    marks = int(np.maximum(odd_upto(jhi) - odd_upto(jlo - 1), 0).sum())
+    return np.maximum(odd_upto(jhi) - odd_upto(jlo - 1), 0)
+
+
+def algorithmic_lds_ops(primes, lo, hi, pmin=FIRST_MARKED_PRIME):
+    """Marks (odd multiples m of each base prime pmin <= p <= isqrt(hi-1) with
+    max(p^2, lo) <= m < hi) plus two LDS accesses per bitmap word (the
+    pre-sieve write and the count read).  With pmin = 37 this is the work of
+    this build, whose pre-sieve covers 3..31; pmin = 7 gives the wheel-30
+    count (only 3 and 5 pre-sieved)."""
+    import numpy as np
+
+    p = np.asarray(primes).astype(np.int64)
+    p = p[(p >= pmin) & (p * p <= hi - 1)]
+    marks = int(_odd_multiples(p, lo, hi).sum())
     words = (hi // 2 - lo // 2 + 31) // 32
     return marks, marks + 2 * words, words
+
+
+def lds_roofline(primes, ranges, seconds):
+    """LDS roofline object for one launch that sieves `ranges` in `seconds`:
+    frac prices this build's own work (marks of primes from 37 up), and
+    frac_wheel30 the wheel-30 work (marks from 7 up) for comparison."""
+    import math
+
+    import numpy as np
+
+    p = np.asarray(primes).astype(np.int64)
+    p = p[p >= 7]
+    n_pre = int(np.searchsorted(p, FIRST_MARKED_PRIME))  # 7..31, struck by the pre-sieve
+    marks = marks30 = words = 0
+    for lo, hi in ranges:
+        if hi <= lo:
+            continue
+        k = int(np.searchsorted(p, math.isqrt(hi - 1), side="right")) if hi > 1 else 0
+        per = _odd_multiples(p[:k], lo, hi)
+        m30 = int(per.sum())
+        marks30 += m30
+        marks += m30 - int(per[:n_pre].sum())
+        words += (hi // 2 - lo // 2 + 31) // 32
+    lane_ops, lane_ops30 = marks + 2 * words, marks30 + 2 * words
+    achieved = lane_ops / seconds
+    return {
+        "bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
+        "unit": "Glane-op/s", "frac": achieved / LDS_PEAK_LANE_OPS,
+        "frac_wheel30": lane_ops30 / seconds / LDS_PEAK_LANE_OPS,
+        "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": words,
+                            "first_marked_prime": FIRST_MARKED_PRIME,
+                            "marks_wheel30": marks30, "lds_lane_ops_wheel30": lane_ops30}}
 
 
 def kernel_source_hash():
@@ -133,21 +220,16 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
            "inputs_sha256": workloads.fingerprint(los, his),
            "ms_per_batch": 1e3 * t_batch, "graph_ms": float(np.mean(kms)), "cold_ms": cold_ms,
            "ints_per_s": ints / t_batch, "pi_sum": int(pi.sum())}
+    rec["_pi"] = pi
     # roofline of the batch graph (reset, batch kernel, reduction, counts
     # copy; the batch kernel dominates): the intervals' algorithmic LDS work
     # over the graph's event-timed duration
     primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(float(his.max()))) + 2)
-    marks = lane_ops = 0
-    for lo, hi in zip(los.tolist(), his.tolist()):
-        m, l, _ = algorithmic_lds_ops(primes, lo, hi)
-        marks += m
-        lane_ops += l
     g_ms = rec["graph_ms"]
-    rec["roofline"] = {
-        "bound": "lds", "achieved": lane_ops / (g_ms * 1e-3) / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
-        "unit": "Glane-op/s", "frac": lane_ops / (g_ms * 1e-3) / LDS_PEAK_LANE_OPS,
-        "traffic": load_traffic("batch-4096"), "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms,
-        "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": total}}
+    roof = lds_roofline(primes, zip(los.tolist(), his.tolist()), g_ms * 1e-3)
+    roof.update({"traffic": load_traffic("batch-4096"),
+                 "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms})
+    rec["roofline"] = roof
     if check_plain:
         # the same outputs, one plain call per interval (pi returned per call)
         base = words.data_ptr()
@@ -240,6 +322,8 @@ def run_mr(sv, torch, steps, warmup, n=1 << 24):
 
 
 def cpu_baseline(lo, hi, expect_pi):
+    """The oracle's count of the whole range on every host thread, and on one
+    thread over the range's last tenth (its densest part)."""
     import oracle  # CPU-baseline leg only
 
     oracle.build(force=False)
@@ -248,9 +332,42 @@ def cpu_baseline(lo, hi, expect_pi):
     pi = oracle.count(lo, hi, threads=threads)
     dt = time.perf_counter() - t0
     assert pi == expect_pi, (pi, expect_pi)
+    lo1 = hi - (hi - lo) // 10
+    t1 = time.perf_counter()
+    oracle.count(lo1, hi, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": (hi - lo) / dt, "unit": "ints/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole workload: oracle count of [{lo}, {hi}) on {threads} threads, "
-                      f"{dt:.2f} s, pi={pi}"}
+                      f"{dt:.2f} s, pi={pi}",
+            "one_thread": {"value": (hi - lo1) / dt1, "unit": "ints/s", "cores": 1,
+                           "sample": f"oracle count of [{lo1}, {hi}) on one thread, {dt1:.2f} s"},
+            "host": host_info(threads)}
+
+
+def batch_cpu_baseline(sv, pi_gpu, n_sample=512):
+    """The oracle's counts of the first n_sample batch intervals on every host
+    thread (one interval at a time), checked against the batch's counts."""
+    import numpy as np
+
+    import oracle  # CPU-baseline leg only
+
+    from paper_1205_4883_amd import workloads
+
+    oracle.build(force=False)
+    threads = oracle.default_threads()
+    los, his = workloads.batch_intervals(0)
+    los, his = los[:n_sample].tolist(), his[:n_sample].tolist()
+    t0 = time.perf_counter()
+    pis = [oracle.count(a, b, threads=threads) for a, b in zip(los, his)]
+    dt = time.perf_counter() - t0
+    assert np.array_equal(np.array(pis, dtype=np.uint64), np.asarray(pi_gpu[:n_sample])), \
+        "oracle and batch counts differ"
+    ints = sum(b - a for a, b in zip(los, his))
+    return {"value": ints / dt, "unit": "ints/s", "cores": threads, "kind": "oracle",
+            "sample": f"counts of the first {n_sample} of the 4096 intervals ({ints} integers), "
+                      f"one interval at a time on {threads} threads, {dt:.2f} s; equal to the "
+                      "batch's counts",
+            "host": host_info(threads)}
 
 
 def main():
@@ -325,6 +442,9 @@ def main():
                      block_threads=args.block_threads)
         b = run_batch(sv, torch, s, args.steps, args.warmup, check_plain=not args.no_plain)
         s.close()
+        pi = b.pop("_pi")
+        if not args.no_cpu:
+            b["cpu_baseline"] = batch_cpu_baseline(sv, pi)
         print(json.dumps({
             "metric": METRIC, "value": b["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_batch"],
@@ -359,27 +479,19 @@ def main():
         kernel_ms.append(sv.sieve_last_kernel_ms(s.ctx))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    device = device_info(torch)  # clock levels right after the timed loop
     assert pi == wl["pi"], pi
     ms_per_step = 1e3 * dt / args.steps
     value = (hi - lo) / (dt / args.steps)
 
     primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(hi)) + 1)
-    marks, lane_ops, words = algorithmic_lds_ops(primes, lo, hi)
     k_ms = float(np.mean(kernel_ms))
-    achieved = lane_ops / (k_ms * 1e-3)
     plan = sv.sieve_plan(lo, hi, tuning=s.tuning())
-    roof = {
-        "bound": "lds",
-        "achieved": achieved / 1e9,
-        "peak": LDS_PEAK_LANE_OPS / 1e9,
-        "unit": "Glane-op/s",
-        "frac": achieved / LDS_PEAK_LANE_OPS,
-        "traffic": load_traffic(args.workload),
-        "kernel": "range_kernel<write=%s>" % ("true" if wl["bitmap"] else "false"),
-        "kernel_ms": k_ms,
-        "kernel_ms_min": float(np.min(kernel_ms)),
-        "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": words},
-    }
+    roof = lds_roofline(primes, [(lo, hi)], k_ms * 1e-3)
+    words = roof["work_per_launch"]["words"]
+    roof.update({"traffic": load_traffic(args.workload),
+                 "kernel": "range_kernel<write=%s>" % ("true" if wl["bitmap"] else "false"),
+                 "kernel_ms": k_ms, "kernel_ms_min": float(np.min(kernel_ms))})
     if wl["bitmap"]:
         roof["hbm_write_GBps"] = 4 * words / (k_ms * 1e-3) / 1e9
     rec = {
@@ -396,9 +508,9 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "cold_ms": cold_ms,
-        "device": device_info(torch),
+        "device": device,
         "config": {"workload": wl["name"], "lo": lo, "hi": hi, "pi": pi,
-                   "presieve_primes": [3, 5, 7, 11, 13, 17, 19, 23, 29, 31],
+                   "presieve_primes": PRESIEVE_PRIMES,
                    "seg_bits": plan["seg_bits"], "dense_limit": plan["dense_limit"],
                    "block_threads": plan["block_threads"], "n_segments": plan["n_segments"]},
         "roofline": roof,
@@ -407,10 +519,14 @@ def main():
         rec["batch"] = run_batch(sv, torch, s, steps=3, warmup=1)
     s.close()
     if args.workload == "count-1e10" and not args.no_batch:
-        rec["serve"] = run_serve(sv, args.serve_seconds or 5.0, modes=("batched",))
+        rec["serve"] = run_serve(sv, args.serve_seconds or 5.0)
         rec["mr"] = run_mr(sv, torch, steps=3, warmup=1)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"])
+        if "batch" in rec:
+            rec["batch"]["cpu_baseline"] = batch_cpu_baseline(sv, rec["batch"]["_pi"])
+    if "batch" in rec:
+        rec["batch"].pop("_pi")
     print(json.dumps(rec), flush=True)
 
 

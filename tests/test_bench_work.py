@@ -1,0 +1,63 @@
+"""CPU checks of the algorithmic work figures the benchmark prices its roofline
+with: closed-form counts of crossed-off odd multiples against enumeration."""
+import math
+
+import numpy as np
+import pytest
+
+import bench
+
+
+def _primes_upto(n):
+    s = np.ones(n + 1, dtype=bool)
+    s[:2] = False
+    for i in range(2, math.isqrt(n) + 1):
+        if s[i]:
+            s[i * i::i] = False
+    return np.nonzero(s)[0].astype(np.uint32)
+
+
+def _enumerated_marks(lo, hi, pmin):
+    """Every odd m in [lo, hi) crossed off by a prime pmin <= p with p^2 <= m,
+    counted once per such prime (the sieve's atomic updates)."""
+    n = 0
+    for p in _primes_upto(max(math.isqrt(max(hi - 1, 0)), 2)).tolist():
+        if p < pmin or p * p > hi - 1:
+            continue
+        for m in range(max(p * p, lo), hi):
+            if m % p == 0 and m % 2 == 1:
+                n += 1
+    return n
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 1), (2, 3), (0, 2000), (2, 10007), (1369, 1370),
+                                   (999, 5000), (40000, 47321), (123457, 130000)])
+def test_marks_match_enumeration(lo, hi):
+    primes = _primes_upto(1000)
+    for pmin in (7, 37):
+        marks, lane_ops, words = bench.algorithmic_lds_ops(primes, lo, hi, pmin=pmin)
+        assert marks == _enumerated_marks(lo, hi, pmin)
+        assert words == (hi // 2 - lo // 2 + 31) // 32
+        assert lane_ops == marks + 2 * words
+    roof = bench.lds_roofline(primes, [(lo, hi)], 1.0)
+    w = roof["work_per_launch"]
+    assert w["marks"] == _enumerated_marks(lo, hi, 37)
+    assert w["marks_wheel30"] == _enumerated_marks(lo, hi, 7)
+
+
+def test_roofline_sums_over_intervals():
+    primes = _primes_upto(2000)
+    ivs = [(10**6, 10**6 + 3001), (5, 5), (2, 99991), (3 * 10**6, 3 * 10**6 + 64)]
+    roof = bench.lds_roofline(primes, ivs, 2.0)
+    w = roof["work_per_launch"]
+    assert w["marks"] == sum(bench.algorithmic_lds_ops(primes, a, b)[0] for a, b in ivs)
+    assert w["marks_wheel30"] == sum(bench.algorithmic_lds_ops(primes, a, b, pmin=7)[0]
+                                     for a, b in ivs)
+    assert w["lds_lane_ops"] == w["marks"] + 2 * w["words"]
+    assert roof["frac"] == pytest.approx(w["lds_lane_ops"] / 2.0 / bench.LDS_PEAK_LANE_OPS)
+    assert roof["frac_wheel30"] > roof["frac"]
+
+
+def test_presieve_set_is_the_odd_primes_below_the_first_marked_one():
+    assert bench.PRESIEVE_PRIMES == [p for p in _primes_upto(bench.FIRST_MARKED_PRIME - 1).tolist()
+                                     if p > 2]
