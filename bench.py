@@ -65,9 +65,12 @@ def _active_level(path):
 
 def device_info(torch):
     """Name, architecture and compute-unit count as the runtime reports them,
-    and the current shader and memory clock levels read from the device's PCI
+    and the active shader and memory clock levels read from the device's PCI
     sysfs node (no helper program is started: under a profiler every child
-    process would inherit its preloaded library)."""
+    process would inherit its preloaded library).  The shader level is the
+    power controller's running average, which includes idle time, so right
+    after a short timed loop it reads well below the clock the kernels ran
+    at."""
     props = torch.cuda.get_device_properties(0)
     info = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
             "compute_units": props.multi_processor_count}
@@ -76,7 +79,7 @@ def device_info(torch):
             props.pci_domain_id, props.pci_bus_id, props.pci_device_id)
     except AttributeError:
         return info
-    for key, fname in (("sclk", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk")):
+    for key, fname in (("sclk_running_avg", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk")):
         level = _active_level(os.path.join(node, fname))
         if level:
             info[key] = level
@@ -293,6 +296,7 @@ def run_mr(sv, torch, steps, warmup, n=1 << 24):
     rng = np.random.default_rng(2)
     ns = rng.integers(0, 2**63, n, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
     s = sv.Sieve(0)
+    sv.sieve_set_timing(s.ctx, True)
     d_n = torch.from_numpy(ns.view(np.int64)).to("cuda:0")
     out = torch.empty(n, dtype=torch.uint8, device="cuda:0")
     stream = torch.cuda.current_stream(0)
@@ -437,6 +441,7 @@ def main():
 
     if args.workload == "batch-4096":
         s = sv.Sieve(0)
+        sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
         if args.seg_bits or args.dense_limit or args.block_threads:
             s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
                      block_threads=args.block_threads)
@@ -455,6 +460,7 @@ def main():
     wl = WORKLOADS[args.workload]
     lo, hi = wl["lo"], wl["hi"]
     s = sv.Sieve(0)
+    sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
     if args.seg_bits or args.dense_limit or args.block_threads:
         s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads)
     stream = torch.cuda.current_stream(0)

@@ -124,11 +124,20 @@ SIEVE_API const char *sieve_strerror(int status);
 /* The hipError_t of the last failed HIP call on this context (0 if none). */
 SIEVE_API int sieve_last_hip_error(const sieve_ctx *ctx);
 
+/* Kernel timing on (on != 0) or off (the default).  While it is on, every
+ * sieve call records a HIP event on its stream immediately before and after
+ * its kernel launch (or batch graph), for sieve_last_kernel_ms; the two
+ * records add a few microseconds to each call, which is why they are off
+ * unless asked for.  Turning it off forgets the last timing.  Errors:
+ * SIEVE_EINVAL (NULL ctx). */
+SIEVE_API int sieve_set_timing(sieve_ctx *ctx, int on);
+
 /* Device time in milliseconds of the last sieve kernel this context launched
- * (sieve_range_count, sieve_range_bitmap or sieve_batch), from HIP events
- * recorded on the call's stream immediately before and after the launch.
- * Waits for that kernel.  Errors: SIEVE_EINVAL (NULL arguments, or no launch
- * yet), SIEVE_EDEVICE. */
+ * while timing was on (sieve_range_count, sieve_range_bitmap, sieve_batch,
+ * sieve_is_prime_batch or sieve_fermat_batch), from the HIP events recorded
+ * around the launch.  Waits for that kernel.  Errors: SIEVE_EINVAL (NULL
+ * arguments, timing off, or no timed launch since it was turned on),
+ * SIEVE_EDEVICE. */
 SIEVE_API int sieve_last_kernel_ms(sieve_ctx *ctx, double *ms);
 
 /* Read or replace the context's tuning.  set validates every field first
@@ -158,7 +167,10 @@ SIEVE_API int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint32_t *out, u
                       uint64_t *n_out);
 
 /* pi over [lo, hi) (steps A1-A6, A8): the number of primes p with
- * lo <= p < hi.  No bitmap is written.  Blocks until *pi_out is valid.
+ * lo <= p < hi.  No bitmap is written.  Blocks until *pi_out is valid: it
+ * returns as soon as the launch's last workgroup has published the count to
+ * pinned host memory, without synchronising `stream` (later work on the
+ * stream stays ordered after the launch).
  * Errors: SIEVE_EINVAL (ctx or pi_out NULL, lo > hi), SIEVE_ERANGE,
  * SIEVE_ENOMEM, SIEVE_EDEVICE. */
 SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *pi_out,
@@ -167,7 +179,8 @@ SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64
 /* The odd-only prime bitmap of [lo, hi) (steps A1-A8) written to the DEVICE
  * buffer d_words[0 .. n_words); words past sieve_bitmap_words(lo, hi) are not
  * touched.  d_words must be 4-byte aligned.  With pi_out == NULL the call is
- * asynchronous (ordered on `stream`); otherwise it blocks and stores pi.
+ * asynchronous (ordered on `stream`); otherwise it synchronises `stream`, so
+ * the words are written when it returns, and stores pi.
  * Errors: SIEVE_EINVAL (ctx NULL, d_words NULL with a non-empty range,
  * misaligned d_words, lo > hi), SIEVE_ERANGE, SIEVE_EBUFSZ (n_words too
  * small), SIEVE_ENOMEM, SIEVE_EDEVICE. */
@@ -206,7 +219,7 @@ SIEVE_API int sieve_batch(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, 
  * they admit no strong pseudoprime, k <= 12 for every n < 2^64; the modular
  * powers are Alg. 2's repeated squaring in Montgomery form.  d_n and d_out
  * are DEVICE arrays of count entries (uint64, uint8).  Asynchronous on
- * `stream`; sieve_last_kernel_ms times it.  Errors: SIEVE_EINVAL (NULL
+ * `stream`; sieve_last_kernel_ms times it (timing on).  Errors: SIEVE_EINVAL (NULL
  * arrays), SIEVE_EDEVICE. */
 SIEVE_API int sieve_is_prime_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, uint8_t *d_out,
                                    void *stream);

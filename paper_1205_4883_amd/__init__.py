@@ -33,6 +33,7 @@ from .sieve import (  # noqa: F401
     sieve_plan,
     sieve_range_bitmap,
     sieve_range_count,
+    sieve_set_timing,
     sieve_set_tuning,
     sieve_strerror,
 )

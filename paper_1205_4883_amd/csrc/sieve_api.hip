@@ -392,7 +392,8 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
         HIP_TRY(c, hipMemsetAsync(overflow, 0, sizeof(uint32_t), s));
         *published(c) = kUnpublished;
         c->ev_valid = false;
-        HIP_TRY(c, hipEventRecord(c->ev_start, s));
+        if (c->timing)
+            HIP_TRY(c, hipEventRecord(c->ev_start, s));
         for (uint64_t w0 = 0; w0 < pl.n_segments; w0 += win) {
             const uint32_t segs = static_cast<uint32_t>(std::min<uint64_t>(win, pl.n_segments - w0));
             const uint64_t word0 = w0 * sw;
@@ -414,8 +415,10 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
                                         resident_blocks(c, wp, d_words != nullptr), s));
         }
         c->slot_dirty[si] = false;
-        HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-        c->ev_valid = true;
+        if (c->timing) {
+            HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+            c->ev_valid = true;
+        }
         uint32_t *h_flag = c->h_ctr + 16;
         HIP_TRY(c, hipMemcpyAsync(h_flag, overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
@@ -444,12 +447,15 @@ namespace {
 // primes is published to *d_pub (a device-visible pinned word) when d_pub is
 // not null.  timed: bracket the launch with the context's timing events.
 int enqueue_plain(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uint32_t *d_words,
-                  unsigned long long *d_pub, hipStream_t s, bool timed, uint32_t n_mark, uint32_t n_dense)
+                  unsigned long long *d_pub, hipStream_t s, bool timed, uint32_t n_mark, uint32_t n_dense,
+                  int *slot_out = nullptr)
 {
     uint32_t *slot = nullptr;
     const int si = take_slot(c, s, &slot);
     if (si < 0)
         return si;
+    if (slot_out)
+        *slot_out = si;
     sv::RangeArgs ra{(lo & ~1ull) + 1, pl.nbits, pl.n_words, d_words, slot, d_pub != nullptr, true,
                      d_pub, nullptr, nullptr, 0};
     sv::PrimeArgs pa{c->d_primes + sv::kPresievePrimes, c->d_inv + sv::kPresievePrimes, n_dense, n_mark};
@@ -468,6 +474,32 @@ int enqueue_plain(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uint32_t
     HIP_TRY(c, hipEventRecord(c->slot_done[si], s));
     c->slot_used[si] = true;
     return SIEVE_OK;
+}
+
+// The count a plain launch in counter slot si publishes: spin on the pinned
+// word, which the launch's last workgroup writes as it leaves, instead of
+// synchronising the stream (the wake-up costs several microseconds).  Every
+// few hundred reads the slot's completion event is queried, so a launch that
+// ends without publishing (a failed launch) is reported instead of waited on
+// forever; the stream is then synchronised to collect its error.
+int wait_published(sieve_ctx *c, int si, hipStream_t s, uint64_t *v)
+{
+    for (uint32_t k = 1;; ++k) {
+        const uint64_t x = *published(c);
+        if (x != kUnpublished) {
+            *v = x;
+            return SIEVE_OK;
+        }
+        if ((k & 255) == 0 && hipEventQuery(c->slot_done[si]) != hipErrorNotReady) {
+            HIP_TRY(c, hipStreamSynchronize(s));
+            const uint64_t y = *published(c);
+            if (y == kUnpublished)
+                return SIEVE_EDEVICE;
+            *v = y;
+            return SIEVE_OK;
+        }
+        __builtin_ia32_pause();
+    }
 }
 
 }  // namespace
@@ -501,13 +533,21 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
     }
     if (pi_out)
         *published(c) = kUnpublished;
-    if (int st = enqueue_plain(c, pl, lo, d_words, pi_out ? c->d_pub : nullptr, s, true, n_mark, n_dense))
+    int si = -1;
+    if (int st = enqueue_plain(c, pl, lo, d_words, pi_out ? c->d_pub : nullptr, s, c->timing, n_mark, n_dense,
+                               &si))
         return st;
     if (pi_out) {
-        HIP_TRY(c, hipStreamSynchronize(s));
-        const uint64_t v = *published(c);
-        if (v == kUnpublished)
-            return SIEVE_EDEVICE;
+        uint64_t v = kUnpublished;
+        if (d_words) {
+            // a bitmap call returns with the words written
+            HIP_TRY(c, hipStreamSynchronize(s));
+            v = *published(c);
+            if (v == kUnpublished)
+                return SIEVE_EDEVICE;
+        } else if (int st = wait_published(c, si, s, &v)) {
+            return st;
+        }
         *pi_out = v + two;
     }
     return SIEVE_OK;
@@ -951,6 +991,16 @@ int sieve_last_hip_error(const sieve_ctx *c)
     return c ? c->last_hip : 0;
 }
 
+int sieve_set_timing(sieve_ctx *c, int on)
+{
+    if (!c)
+        return SIEVE_EINVAL;
+    c->timing = on != 0;
+    if (!c->timing)
+        c->ev_valid = false;
+    return SIEVE_OK;
+}
+
 int sieve_last_kernel_ms(sieve_ctx *c, double *ms)
 {
     if (!c || !ms || !c->ev_valid)
@@ -1049,7 +1099,7 @@ int sieve_batch(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t *d_
     if (int st = sv::engine_stage(c, c->batch, iv, n, d_words, total_words))
         return st;
     hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
-    if (int st = sv::engine_launch(c, c->batch, d_words, s, true))
+    if (int st = sv::engine_launch(c, c->batch, d_words, s, c->timing))
         return st;
     SV_HIP_TRY(c, hipEventSynchronize(c->batch.done));
     c->batch.pending = false;
@@ -1097,6 +1147,8 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
     const SegChoice segs[] = {{1u << 17, 512}, {1u << 18, 512}, {1u << 19, 1024}, {1u << 20, 1024}};
     const uint32_t dense_div[] = {1024, 512, 256};
     const sieve_tuning saved = c->tuning;
+    const bool saved_timing = c->timing;
+    c->timing = true;  // candidates are ranked by their kernel times
     std::vector<sieve_interval> count_only(iv, iv + n);
     for (auto &v : count_only)
         v.flags = 0;
@@ -1136,6 +1188,9 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             break;
     }
     c->tuning = saved;
+    c->timing = saved_timing;
+    if (!saved_timing)
+        c->ev_valid = false;
     if (st != SIEVE_OK)
         return st;
     c->tune_cache[key] = {win, win_ms};

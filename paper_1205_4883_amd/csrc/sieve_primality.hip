@@ -328,10 +328,13 @@ int sieve_is_prime_batch(sieve_ctx *c, const uint64_t *d_n, uint64_t count, uint
     const uint64_t want = (count + sv::kMrChunk - 1) / sv::kMrChunk;  // one chunk per workgroup pass
     const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 16ull * c->n_cu));
     c->ev_valid = false;
-    SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    if (c->timing)
+        SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
     SV_HIP_TRY(c, sv::launch_is_prime(d_n, count, d_out, blocks, s));
-    SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-    c->ev_valid = true;
+    if (c->timing) {
+        SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+        c->ev_valid = true;
+    }
     return SIEVE_OK;
 }
 
@@ -347,10 +350,13 @@ int sieve_fermat_batch(sieve_ctx *c, const uint64_t *d_n, uint64_t count, const 
     const uint64_t want = (count + 255) / 256;
     const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>(want, 64ull * c->n_cu));
     c->ev_valid = false;
-    SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
+    if (c->timing)
+        SV_HIP_TRY(c, hipEventRecord(c->ev_start, s));
     SV_HIP_TRY(c, sv::launch_fermat(d_n, count, d_draws, iterations, d_out, blocks, s));
-    SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
-    c->ev_valid = true;
+    if (c->timing) {
+        SV_HIP_TRY(c, hipEventRecord(c->ev_stop, s));
+        c->ev_valid = true;
+    }
     return SIEVE_OK;
 }
 

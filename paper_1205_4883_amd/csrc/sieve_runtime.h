@@ -103,9 +103,12 @@ struct sieve_ctx {
     uint32_t *h_ctr = nullptr;
     unsigned long long *d_pub = nullptr;
 
-    // events bracketing the last sieve kernel launch (range or batch)
+    // events bracketing the last sieve kernel launch (range, batch or
+    // primality), recorded only while timing is on (two event records cost
+    // a few microseconds per call)
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     bool ev_valid = false;
+    bool timing = false;
 
     sv::BatchEngine batch;
 

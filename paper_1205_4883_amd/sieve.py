@@ -26,7 +26,7 @@ SIEVE_WANT_BITMAP = 1
 
 EXPORTED = [
     "sieve_create", "sieve_destroy", "sieve_strerror", "sieve_last_hip_error",
-    "sieve_last_kernel_ms",
+    "sieve_set_timing", "sieve_last_kernel_ms",
     "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
     "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
     "sieve_autotune", "sieve_is_prime_batch", "sieve_fermat_batch",
@@ -109,6 +109,7 @@ def _lib():
     lib.sieve_strerror.argtypes = [i32]
     lib.sieve_strerror.restype = ctypes.c_char_p
     lib.sieve_last_hip_error.argtypes = [vp]
+    lib.sieve_set_timing.argtypes = [vp, i32]
     lib.sieve_last_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.sieve_get_tuning.argtypes = [vp, ctypes.POINTER(sieve_tuning)]
     lib.sieve_set_tuning.argtypes = [vp, ctypes.POINTER(sieve_tuning)]
@@ -162,6 +163,10 @@ def sieve_strerror(status):
 
 def sieve_last_hip_error(ctx):
     return _lib().sieve_last_hip_error(ctx)
+
+
+def sieve_set_timing(ctx, on):
+    _check(_lib().sieve_set_timing(ctx, 1 if on else 0), "sieve_set_timing")
 
 
 def sieve_last_kernel_ms(ctx):

@@ -430,3 +430,67 @@ def test_buckets_off_and_on_agree(gpu, sv_mod):
     finally:
         gpu.tuning(bucket_limit=0)
     assert p0 == p1 and np.array_equal(a, w1.cpu().numpy())
+
+
+# -- kernel timing switch and the count call's early return ---------------------
+
+def test_timing_is_off_by_default_and_switches(gpu, oracle_mod, sv_mod):
+    import torch
+
+    print("case timing switch", flush=True)
+    s = sv_mod.Sieve(0)
+    try:
+        assert s.count(2, 10**6) == 78498
+        with pytest.raises(sv_mod.SieveError) as e:
+            sv_mod.sieve_last_kernel_ms(s.ctx)  # never timed
+        assert e.value.status == sv_mod.sieve.SIEVE_EINVAL
+        sv_mod.sieve_set_timing(s.ctx, True)
+        assert s.count(2, 10**8) == 5761455
+        assert sv_mod.sieve_last_kernel_ms(s.ctx) > 0
+        words, pi = s.bitmap(10**9, 10**9 + 10**7)
+        assert pi == oracle_mod.count(10**9, 10**9 + 10**7)
+        assert sv_mod.sieve_last_kernel_ms(s.ctx) > 0
+        pis = s.batch(np.array([10**6, 10**10], dtype=np.uint64), np.array([10**6 + 99991, 10**10 + 10**6],
+                                                                           dtype=np.uint64))
+        assert int(pis[0]) == oracle_mod.count(10**6, 10**6 + 99991)
+        assert sv_mod.sieve_last_kernel_ms(s.ctx) > 0
+        n = torch.tensor([97, 91, 2**61 - 1], dtype=torch.int64, device="cuda:0")
+        out = torch.empty(3, dtype=torch.uint8, device="cuda:0")
+        sv_mod.sieve_is_prime_batch(s.ctx, n, 3, out)
+        torch.cuda.synchronize()
+        assert out.cpu().tolist() == [1, 0, 1]
+        assert sv_mod.sieve_last_kernel_ms(s.ctx) > 0
+        sv_mod.sieve_set_timing(s.ctx, False)
+        with pytest.raises(sv_mod.SieveError):
+            sv_mod.sieve_last_kernel_ms(s.ctx)  # forgotten when turned off
+        assert s.count(2, 10**7) == 664579
+        with pytest.raises(sv_mod.SieveError):
+            sv_mod.sieve_last_kernel_ms(s.ctx)
+        # the autotuner times its candidates and leaves timing as it found it
+        sv_mod.sieve_autotune(s.ctx, [10**8], [10**8 + 10**7], apply=False)
+        with pytest.raises(sv_mod.SieveError):
+            sv_mod.sieve_last_kernel_ms(s.ctx)
+    finally:
+        s.close()
+
+
+def test_count_calls_back_to_back_on_one_stream(gpu, oracle_mod, sv_mod):
+    # count calls return on the published count without synchronising the
+    # stream; a run of them on one stream, of every length from a single
+    # segment to thousands, with bitmap calls between, must each be exact
+    import torch
+
+    print("case back-to-back counts", flush=True)
+    stream = torch.cuda.Stream(0)
+    rng = random.Random(5)
+    cases = [(2, 10**10), (0, 3), (10**12, 10**12 + 64), (7, 10**9)]
+    cases += [(a, a + rng.randrange(1, 10**rng.randrange(2, 9))) for a in
+              (rng.randrange(0, 10**rng.randrange(3, 14)) for _ in range(40))]
+    words = torch.empty(sv_mod.sieve_bitmap_words(0, 10**6), dtype=torch.int32, device="cuda:0")
+    for i, (lo, hi) in enumerate(cases):
+        pi = sv_mod.sieve_range_count(gpu.ctx, lo, hi, stream=stream)
+        assert pi == oracle_mod.count(lo, hi), (lo, hi)
+        if i % 5 == 0:
+            p2 = sv_mod.sieve_range_bitmap(gpu.ctx, 0, 10**6, words, words.numel(), True, stream=stream)
+            assert p2 == 78498
+    stream.synchronize()
