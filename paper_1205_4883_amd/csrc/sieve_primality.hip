@@ -80,13 +80,33 @@ __device__ __forceinline__ uint64_t mont_pow(const Mont &m, uint64_t base_m, uin
     return x;
 }
 
-// One Miller-Rabin round on a base already in Montgomery form (a R mod n,
-// a not divisible by n): n - 1 = d * 2^s, d odd.  True when the base does
-// not prove n composite.
-__device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a_m, uint64_t d, int s)
+// x + y mod n for x, y < n (the sum may pass 2^64).
+__device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t n)
+{
+    const uint64_t s = x + y;
+    return (s < x || s >= n) ? s - n : s;
+}
+
+// 2^e in Montgomery form (2^e R mod n), e >= 1, by left-to-right repeated
+// squaring: the same squarings as mont_pow, but a set bit of e multiplies by
+// the base 2, which is one modular doubling instead of a product.
+__device__ __forceinline__ uint64_t mont_pow2(const Mont &m, uint64_t e)
+{
+    int k = 63 - __clzll(e);              // the top bit of e ...
+    uint64_t x = add_mod(m.one, m.one, m.n);  // ... is the base itself: 2R mod n
+    while (k-- > 0) {
+        x = mont_mul(m, x, x);
+        if ((e >> k) & 1)
+            x = add_mod(x, x, m.n);
+    }
+    return x;
+}
+
+// The end of a Miller-Rabin round from x = a^d R mod n (n - 1 = d * 2^s, d
+// odd): true when the base does not prove n composite.
+__device__ __forceinline__ bool mr_finish(const Mont &m, uint64_t x, int s)
 {
     const uint64_t minus_one = m.n - m.one;  // (n - 1) R mod n
-    uint64_t x = mont_pow(m, a_m, d);
     if (x == m.one || x == minus_one)
         return true;
     for (int j = 1; j < s; ++j) {
@@ -97,11 +117,33 @@ __device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a_m, uint64_t d
     return false;
 }
 
-// x + y mod n for x, y < n (the sum may pass 2^64).
-__device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t n)
+// a^e in Montgomery form by left-to-right repeated squaring over fixed
+// two-bit windows of e: each window squares twice and multiplies once by
+// 1, a, a^2 or a^3 (the product by 1 = R mod n leaves x as it is).  Every
+// lane runs the same 32 windows, so a wavefront of different exponents
+// never diverges; the right-to-left loop of mont_pow multiplies only on set
+// bits, but across 64 lanes some lane almost always has one, so a wavefront
+// pays the product on nearly every bit.
+__device__ __forceinline__ uint64_t mont_pow_w2(const Mont &m, uint64_t a_m, uint64_t e)
 {
-    const uint64_t s = x + y;
-    return (s < x || s >= n) ? s - n : s;
+    const uint64_t a2 = mont_mul(m, a_m, a_m);
+    const uint64_t a3 = mont_mul(m, a2, a_m);
+    uint64_t x = m.one;
+    for (int k = 62; k >= 0; k -= 2) {
+        x = mont_mul(m, x, x);
+        x = mont_mul(m, x, x);
+        const uint32_t w = static_cast<uint32_t>(e >> k) & 3u;
+        const uint64_t t = (w & 2) ? ((w & 1) ? a3 : a2) : ((w & 1) ? a_m : m.one);
+        x = mont_mul(m, x, t);
+    }
+    return x;
+}
+
+// One Miller-Rabin round on a base already in Montgomery form (a R mod n,
+// a not divisible by n).
+__device__ __forceinline__ bool mr_round(const Mont &m, uint64_t a_m, uint64_t d, int s)
+{
+    return mr_finish(m, mont_pow_w2(m, a_m, d), s);
 }
 
 // Deterministic Miller-Rabin for n < 2^64, in three stages so that the
@@ -136,16 +178,50 @@ __device__ __forceinline__ int mr_rounds(uint64_t n, bool &wide)
     return 7;
 }
 
+// Divisibility by an odd constant p without a division (Granlund and
+// Montgomery, 1994): multiplying by p^-1 mod 2^64 maps the multiples of p
+// onto [0, (2^64 - 1) / p] and every other n above it.
+struct DivTest {
+    uint64_t inv;  // p^-1 mod 2^64
+    uint64_t lim;  // (2^64 - 1) / p
+};
+
+constexpr uint64_t inverse_mod_2_64(uint64_t p)
+{
+    uint64_t inv = p;  // correct to 3 bits for odd p
+    for (int i = 0; i < 5; ++i)
+        inv *= 2 - p * inv;
+    return inv;
+}
+
+struct DivTests {
+    DivTest t[12];
+};
+
+constexpr DivTests make_div_tests()
+{
+    DivTests d{};
+    for (int i = 1; i < 12; ++i)  // the odd small bases 3..37
+        d.t[i] = DivTest{inverse_mod_2_64(kSmallBases[i]), ~0ull / kSmallBases[i]};
+    return d;
+}
+
+constexpr DivTests kDivTests = make_div_tests();
+static_assert(3ull * kDivTests.t[1].inv == 1 && 37ull * kDivTests.t[11].inv == 1, "inverses mod 2^64");
+
 // Stage 1: 0 = composite, 1 = prime, 2 = undecided (no factor up to 37,
 // n >= 41^2).
 __device__ __forceinline__ uint32_t mr_stage1(uint64_t n)
 {
     if (n < 2)
         return 0;
-    for (int i = 0; i < 12; ++i) {
+    if ((n & 1) == 0)
+        return n == 2 ? 1 : 0;
+#pragma unroll
+    for (int i = 1; i < 12; ++i) {
         if (n == kSmallBases[i])
             return 1;
-        if (n % kSmallBases[i] == 0)
+        if (n * kDivTests.t[i].inv <= kDivTests.t[i].lim)
             return 0;
     }
     return n < 41 * 41 ? 1 : 2;  // no factor up to 37 and below 41^2: prime
@@ -162,15 +238,15 @@ __device__ __forceinline__ void mr_split(uint64_t n, uint64_t &d, int &s)
 }
 
 // Stage 2, for an undecided n: the base-2 round, which rejects almost every
-// composite (the Montgomery form of 2 is one modular doubling of R mod n).
-// 0 = composite, 1 = prime (base 2 is all n < 2047 needs), 2 = undecided.
+// composite (2^d by squaring and doubling, see mont_pow2).  0 = composite,
+// 1 = prime (base 2 is all n < 2047 needs), 2 = undecided.
 __device__ __forceinline__ uint32_t mr_stage2(uint64_t n)
 {
     uint64_t d;
     int s;
     mr_split(n, d, s);
     const Mont m = mont_setup(n);
-    if (!mr_round(m, add_mod(m.one, m.one, n), d, s))
+    if (!mr_finish(m, mont_pow2(m, d), s))
         return 0;
     bool wide;
     return mr_rounds(n, wide) == 1 ? 1 : 2;
