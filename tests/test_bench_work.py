@@ -61,3 +61,29 @@ def test_roofline_sums_over_intervals():
 def test_presieve_set_is_the_odd_primes_below_the_first_marked_one():
     assert bench.PRESIEVE_PRIMES == [p for p in _primes_upto(bench.FIRST_MARKED_PRIME - 1).tolist()
                                      if p > 2]
+
+
+def test_committed_counter_runs_are_sane():
+    # the rocprofv3 byte counts behind the roofline's traffic figures must
+    # at least cover the output each launch writes, and a count-only launch
+    # must write far less than the bitmap it never stores
+    import json
+    import os
+
+    prof = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles")
+
+    def rec(name):
+        with open(os.path.join(prof, f"traffic_{name}.json")) as f:
+            return json.load(f)
+
+    bitmap = rec("bitmap-1e9")
+    assert bitmap["hbm_write_bytes_per_launch"] >= 4 * 15_625_000
+    assert bitmap["hbm_write_bytes_per_launch"] < 2 * 4 * 15_625_000
+    batch = rec("batch-4096")
+    assert batch["hbm_write_bytes_per_launch"] >= 2_801_070_496
+    count = rec("count-1e10")
+    assert count["hbm_write_bytes_per_launch"] < 0.05 * 4 * 156_250_000
+    for r in (bitmap, batch, count):
+        cal = r["copy_calibration"]
+        # the copy kernel reads and writes 256 MiB: both scales near 1 or 2
+        assert 0.9 < cal["write_scale"] < 2.1 and 0.9 < cal["fetch_scale"] < 2.1

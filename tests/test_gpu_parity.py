@@ -185,6 +185,47 @@ def test_additivity_on_gpu(gpu):
         assert gpu.count(a, c) == gpu.count(a, b) + gpu.count(b, c)
 
 
+def test_properties_of_a_large_range_near_the_top(gpu):
+    # at a size the oracle is not run on: [1e15 - 2^33, 1e15) (2^32 odd
+    # integers, 512 MiB of bitmap).  The words of [a, b) and [b, c) (b at a
+    # multiple of 64 from a) concatenate to those of [a, c); the count equals
+    # the bitmap's popcount; sampled set bits are prime and sampled clear
+    # bits composite by the GPU's own Miller-Rabin.
+    print("case large-range properties below 1e15", flush=True)
+    torch = gpu.torch
+    a, c = 10**15 - 2**33, 10**15
+    b = a + 64 * 50_000_017
+    w_ac, pi_ac = gpu.bitmap(a, c)
+    w_ab, pi_ab = gpu.bitmap(a, b)
+    w_bc, pi_bc = gpu.bitmap(b, c)
+    assert pi_ac == pi_ab + pi_bc == gpu.count(a, c)
+    assert torch.equal(w_ac, torch.cat([w_ab, w_bc]))
+    del w_ab, w_bc
+    # popcount in chunks (the whole bitmap as int64 bit counts would need GBs)
+    total = 0
+    u8 = w_ac.view(torch.uint8)
+    table = torch.tensor([bin(i).count("1") for i in range(256)], dtype=torch.int64, device=w_ac.device)
+    for k in range(0, u8.numel(), 1 << 26):
+        total += int(table[u8[k:k + (1 << 26)].long()].sum())
+    assert total == pi_ac  # no 2 in range
+    rng = random.Random(17)
+    words = w_ac.cpu().numpy().view(np.uint32)
+    ns, want = [], []
+    base = (a & ~1) + 1
+    for _ in range(4000):
+        i = rng.randrange(0, words.size * 32)
+        n = base + 2 * i
+        if n >= c:
+            continue
+        ns.append(n)
+        want.append(bool((words[i >> 5] >> (i & 31)) & 1))
+    assert any(want) and not all(want)
+    got = gpu.is_prime(ns)
+    assert got.tolist() == want
+    del w_ac
+    torch.cuda.empty_cache()
+
+
 # -- base primes -------------------------------------------------------------
 
 @pytest.mark.parametrize("limit", [0, 1, 2, 3, 100, 65535, 65536, 100000, 2**20, 3 * 10**6, 31622777])
