@@ -30,6 +30,7 @@
 // per dense mark at one add.
 #include <atomic>
 
+#include "dense_layout.h"
 #include "sieve_internal.h"
 
 namespace sv {
@@ -95,6 +96,22 @@ constexpr PresieveTables make_tables()
 }
 
 __constant__ PresieveTables kTables = make_tables();
+
+// Per dense prime, the lane layout of its wheel classes (see mark_dense).
+struct DenseStrides {
+    uint8_t u[kDenseStrideCount];
+};
+
+constexpr DenseStrides make_dense_strides()
+{
+    DenseStrides d{};
+    for (uint32_t i = 0; i < kDenseStrideCount; ++i)
+        d.u[i] = kDenseStride[i];
+    return d;
+}
+
+__constant__ DenseStrides kDenseStrides = make_dense_strides();
+static_assert(kFirstMarkedPrime == 37, "kDenseStride is indexed from the prime 37");
 
 // Copy the tables into the workgroup's LDS (visible after its next barrier).
 __device__ __forceinline__ void build_tables(uint32_t *tabs)
@@ -182,26 +199,34 @@ __device__ __forceinline__ uint32_t wheel_start(uint32_t p, uint32_t &o, uint32_
 // p*m with m prime to 15 are crossed off (3 | m or 5 | m is already covered
 // by the pre-sieve).  Counting odd multiples i = 0, 1, ... from the first
 // such m, the kept i repeat with period 15 (8 per period), so over 480 odd
-// steps there are 256 kept classes: lane l takes c_l + 120 j, j = 0..3,
-// where c_l is the l-th kept class below 120.  480*p bits is a whole number
-// of words (15p), so each of a lane's four classes keeps a fixed bit and
-// moves by 15p words per mark: one LDS atomic OR and one add.  Lane 63 has
-// the largest class, so its fourth class drives the loop (a scalar), and each
-// lane needs at most four guarded marks after it.
+// steps there are 256 kept classes; the k-th of them (k = 0..255) is
+// 15 (k / 8) + (the sum of the first k mod 8 gaps of the rotated cycle).
+// Lane l takes in slot j = 0..3 the class with k = u (l + 64 j) mod 256:
+// u is odd, so the 64 x 4 (lane, slot) pairs take every class once, and a
+// lane's four classes lie 120 odd steps apart in some order.  480*p bits is
+// a whole number of words (15p), so each class keeps a fixed bit and moves by
+// 15p words per mark: one LDS atomic OR and one add.  u is chosen per prime
+// (kDenseStrides) so that the 32 lanes of each half-wavefront spread over
+// the LDS banks.  The largest class (fixed by the cycle alone) drives the
+// loop (a scalar), and each class needs at most one guarded mark after it.
 __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t p, uint32_t s,
-                                           uint32_t m30, uint32_t lane)
+                                           uint32_t m30, uint32_t lane, uint32_t u)
 {
     uint32_t o = s;
     const uint32_t idx = wheel_start(p, o, m30);
     const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
-    // c_l = 15 (l / 8) + (sum of the first l mod 8 gaps of the rotated cycle)
-    const uint32_t first = g & ((1u << (2 * (lane & 7))) - 1);
-    const uint32_t e = __popc(first & 0x5555u) + 2 * __popc(first & 0xaaaau);
-    const uint32_t c = 15 * (lane >> 3) + e;
+    const uint32_t k0 = (u * lane) & 255u;
+    const uint32_t first = g & ((1u << (2 * (k0 & 7))) - 1);
+    const uint32_t e = __popc(first & 0x5555u) + 2 * __popc(first & 0xaaaau);  // k mod 8 = k0 mod 8
+    const uint32_t ku = 64u * u;
+    const uint32_t k1 = (k0 + ku) & 255u, k2 = (k0 + 2 * ku) & 255u, k3 = (k0 + 3 * ku) & 255u;
     const uint32_t c63 = 105 + 15 - ((g >> 14) & 3);  // the eight gaps sum to 15
-    const uint32_t q = 120 * p;                       // bits between a lane's classes
-    const uint32_t x0 = o + __umul24(c, p);           // dense primes are below 2^20
-    const uint32_t x1 = x0 + q, x2 = x1 + q, x3 = x2 + q;
+    const uint32_t q = 120 * p;                       // odd steps between a lane's classes, in bits
+    // dense primes are below 2^20 and classes below 480: full-rate 24-bit products
+    const uint32_t x0 = o + __umul24(15 * (k0 >> 3) + e, p);
+    const uint32_t x1 = o + __umul24(15 * (k1 >> 3) + e, p);
+    const uint32_t x2 = o + __umul24(15 * (k2 >> 3) + e, p);
+    const uint32_t x3 = o + __umul24(15 * (k3 >> 3) + e, p);
     uint32_t *p0 = seg + (x0 >> 5);
     uint32_t *p1 = seg + (x1 >> 5);
     uint32_t *p2 = seg + (x2 >> 5);
@@ -410,17 +435,19 @@ __device__ __forceinline__ void seg_dense(uint32_t *seg_lds, const SegGeom &g, c
     const uint32_t nw = blockDim.x >> 6;
     for (uint32_t r0 = 0; r0 + wave < n_dense; r0 += 64 * nw) {
         const uint32_t i = r0 + lane * nw + wave;
-        uint32_t p = 0, s0 = 0, m30 = 0;
+        uint32_t p = 0, s0 = 0, m30 = 0, u = 1;
         if (i < n_dense) {
             p = primes[i];
             const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
             s0 = st.off;
             m30 = st.m30;
+            if (i < kDenseStrideCount)
+                u = kDenseStrides.u[i];
         }
         const uint32_t cnt = min(64u, (n_dense - r0 - wave + nw - 1) / nw);
         for (uint32_t l = 0; l < cnt; ++l)
             mark_dense(seg_lds, g.sw, __builtin_amdgcn_readlane(p, l), __builtin_amdgcn_readlane(s0, l),
-                       __builtin_amdgcn_readlane(m30, l), lane);
+                       __builtin_amdgcn_readlane(m30, l), lane, __builtin_amdgcn_readlane(u, l));
     }
 }
 
