@@ -108,6 +108,19 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
             pw *= 2;
         sw = static_cast<uint32_t>(std::min<uint64_t>(pw, cap));
     }
+    if (!t.seg_bits && sw == kDefaultMaxSegWords && max_seg_words(lds_bytes) >= kWideSegWords) {
+        // Long ranges without hit buckets take the widest segment (same
+        // occupancy, less set-up per integer; measured 0.74 -> 0.70 ms on
+        // [2, 1e10)).  Shorter ranges keep 2^19 bits: with under four rounds
+        // of two workgroups per CU a wider segment mostly lengthens the last
+        // round.
+        const uint64_t sb = static_cast<uint64_t>(sw) * 32;
+        const bool buckets = t.bucket_limit != 0xffffffffu &&
+                             (t.bucket_limit ? true : 2 * p.sqrt_bound >= 3 * sb && p.nbits >= (1ull << 30));
+        const uint64_t n_pow2 = (p.n_words + sw - 1) / sw;
+        if (!buckets && n_pow2 >= 8ull * n_cu)
+            sw = kWideSegWords;
+    }
     p.seg_bits = sw * 32;
     p.dense_limit = t.dense_limit ? t.dense_limit : default_dense_limit(p.seg_bits);
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
@@ -1144,7 +1157,7 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
     struct SegChoice {
         uint32_t seg_bits, threads;
     };
-    const SegChoice segs[] = {{1u << 17, 512}, {1u << 18, 512}, {1u << 19, 1024}, {1u << 20, 1024}};
+    const SegChoice segs[] = {{1u << 17, 512}, {1u << 18, 512}, {1u << 19, 1024}, {sv::kWideSegWords * 32, 1024}};
     const uint32_t dense_div[] = {1024, 512, 256};
     const sieve_tuning saved = c->tuning;
     const bool saved_timing = c->timing;

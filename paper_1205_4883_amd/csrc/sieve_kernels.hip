@@ -971,7 +971,9 @@ __global__ void __launch_bounds__(256) reciprocal_kernel(const uint32_t *primes,
 }
 
 // Static LDS sizes the segment kernels are built for (words of segment).
-constexpr uint32_t kSegSizes[] = {512, 2048, 8192, 16384, 32768};
+constexpr uint32_t kSegSizes[] = {512, 2048, 8192, 16384, kWideSegWords};
+static_assert(2 * ((kTableWords + kWideSegWords) * 4 + 1024) <= 160 * 1024,
+              "two workgroups of the widest segment per CU");
 
 }  // namespace
 
@@ -1069,7 +1071,7 @@ uint32_t cap_index(uint32_t cap)
     case 2048: return 2;
     case 8192: return 3;
     case 16384: return 4;
-    case 32768: return 5;
+    case kWideSegWords: return 5;
     default: return 0;
     }
 }
@@ -1099,7 +1101,7 @@ uint32_t range_blocks_per_cu(uint32_t seg_words, uint32_t threads, bool write)
     case 2048: return write ? blocks_per_cu(range_kernel<2048, true>, threads, kind, cap) : blocks_per_cu(range_kernel<2048, false>, threads, kind, cap);
     case 8192: return write ? blocks_per_cu(range_kernel<8192, true>, threads, kind, cap) : blocks_per_cu(range_kernel<8192, false>, threads, kind, cap);
     case 16384: return write ? blocks_per_cu(range_kernel<16384, true>, threads, kind, cap) : blocks_per_cu(range_kernel<16384, false>, threads, kind, cap);
-    case 32768: return write ? blocks_per_cu(range_kernel<32768, true>, threads, kind, cap) : blocks_per_cu(range_kernel<32768, false>, threads, kind, cap);
+    case kWideSegWords: return write ? blocks_per_cu(range_kernel<kWideSegWords, true>, threads, kind, cap) : blocks_per_cu(range_kernel<kWideSegWords, false>, threads, kind, cap);
     default: return 1;
     }
 }
@@ -1112,7 +1114,7 @@ uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
     case 2048: return blocks_per_cu(batch_kernel<2048, true>, threads, 2, cap);
     case 8192: return blocks_per_cu(batch_kernel<8192, true>, threads, 2, cap);
     case 16384: return blocks_per_cu(batch_kernel<16384, true>, threads, 2, cap);
-    case 32768: return blocks_per_cu(batch_kernel<32768, true>, threads, 2, cap);
+    case kWideSegWords: return blocks_per_cu(batch_kernel<kWideSegWords, true>, threads, 2, cap);
     default: return 1;
     }
 }
@@ -1147,7 +1149,7 @@ hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_wor
     case 2048: launch_range_cap<2048>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
     case 8192: launch_range_cap<8192>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
     case 16384: launch_range_cap<16384>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
-    case 32768: launch_range_cap<32768>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
+    case kWideSegWords: launch_range_cap<kWideSegWords>(r, p, seg_words, block_threads, n_segments, chunk, n_chunks, grid, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1185,7 +1187,7 @@ hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint3
     case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
     case 8192: launch_batch_cap<8192>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
     case 16384: launch_batch_cap<16384>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
-    case 32768: launch_batch_cap<32768>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
+    case kWideSegWords: launch_batch_cap<kWideSegWords>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
     default: return hipErrorInvalidValue;
     }
     const uint32_t waves_blocks = (max_intervals + 3) / 4;  // four wavefronts per block

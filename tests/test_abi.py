@@ -69,10 +69,19 @@ def test_plan_tuning_resolution():
     assert p["seg_bits"] == 65536 and p["dense_limit"] == 500 and p["block_threads"] == 512
     p = sv.sieve_plan(2, 10**10, tuning=dict(dense_limit=3))
     assert p["dense_limit"] == 37
-    # defaults: the largest LDS segment (2^19 bits) for long ranges, with
-    # 1024 threads; smaller segments take fewer threads
+    # defaults: 2^19-bit segments with 1024 threads once a range fills the
+    # chip; the widest segment (622,592 bits, still two workgroups per CU)
+    # from four rounds of 2^19-bit segments (8 per CU) when no hit buckets
+    # are wanted; smaller segments take fewer threads
     p = sv.sieve_plan(2, 10**10)
+    assert p["seg_bits"] == 622592 and p["block_threads"] == 1024 and p["dense_limit"] == 1216
+    p = sv.sieve_plan(2, 10**9)  # 954 segments of 2^19 bits: under four rounds
     assert p["seg_bits"] == 1 << 19 and p["block_threads"] == 1024 and p["dense_limit"] == 1024
+    assert sv.sieve_plan(0, 2 * 2048 * 2**19)["seg_bits"] == 622592         # exactly 2048 segments
+    assert sv.sieve_plan(0, 2 * 2047 * 2**19)["seg_bits"] == 1 << 19       # 2047 segments
+    assert sv.sieve_plan(2, 10**10, n_cu=64)["seg_bits"] == 622592
+    # a device with 64 KiB of LDS per workgroup holds 2^18-bit segments at most
+    assert sv.sieve_plan(2, 10**10, lds_bytes=65536)["seg_bits"] == 1 << 18
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 18))
     assert p["block_threads"] == 512
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 15))
@@ -84,10 +93,15 @@ def test_plan_tuning_resolution():
     # at least 2^30 odd integers
     assert sv.sieve_plan(10**12, 10**12 + 10**10)["bucket_limit"] == 1 << 19
     assert sv.sieve_plan(10**11, 10**11 + 10**10)["bucket_limit"] == 0
+    assert sv.sieve_plan(10**11, 10**11 + 10**10)["seg_bits"] == 622592
+    assert sv.sieve_plan(10**12, 10**12 + 10**10)["seg_bits"] == 1 << 19  # buckets keep 2^19
     assert sv.sieve_plan(10**12, 10**12 + 2**31 - 2)["bucket_limit"] == 0
     assert sv.sieve_plan(10**12, 10**12 + 2**31)["bucket_limit"] == 1 << 19
     assert sv.sieve_plan(10**11, 10**11 + 10**6)["bucket_limit"] == 0
-    assert sv.sieve_plan(10**12, 10**12 + 10**10, tuning=dict(bucket_limit=0xFFFFFFFF))["bucket_limit"] == 0
+    p = sv.sieve_plan(10**12, 10**12 + 10**10, tuning=dict(bucket_limit=0xFFFFFFFF))
+    assert p["bucket_limit"] == 0 and p["seg_bits"] == 622592
+    # the widest segment can be asked for; anything wider cannot
+    assert sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=622592))["seg_bits"] == 622592
 
 
 @pytest.mark.parametrize("lo,hi,tuning,status", [
@@ -95,6 +109,8 @@ def test_plan_tuning_resolution():
     (0, 10**15 + 1, None, -2),
     (0, 100, dict(seg_bits=1000), -1),
     (0, 100, dict(seg_bits=2**30), -1),
+    (0, 100, dict(seg_bits=622592 + 4096), -1),
+    (0, 100, dict(seg_bits=1 << 20), -1),
     (0, 100, dict(block_threads=100), -1),
     (0, 100, dict(dense_limit=2**21), -1),
 ])

@@ -144,6 +144,7 @@ def test_segment_boundary_straddles(gpu, oracle_mod):
 @pytest.mark.parametrize("seg_bits,dense_limit,threads", [
     (4096, 37, 256), (4096, 64, 512), (32768, 0, 1024), (131072, 37, 256),
     (524288, 0, 1024), (524288, 37, 1024), (524288, 2**20, 1024), (262144, 1000, 512),
+    (622592, 0, 1024), (622592, 2048, 1024),
 ])
 def test_tuning_sweep(gpu, oracle_mod, seg_bits, dense_limit, threads):
     gpu.tuning(seg_bits=seg_bits, dense_limit=dense_limit, block_threads=threads)
@@ -355,7 +356,7 @@ def test_batch_graph_replays_and_shrinks(gpu, oracle_mod):
             assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), (n, i)
 
 
-@pytest.mark.parametrize("seg_bits,threads", [(4096, 256), (65536, 256), (1048576, 1024)])
+@pytest.mark.parametrize("seg_bits,threads", [(4096, 256), (65536, 256), (622592, 1024)])
 def test_batch_tunings(gpu, oracle_mod, seg_bits, threads):
     rng = np.random.default_rng(seg_bits)
     los = np.floor(np.exp(rng.uniform(0, np.log(1e11), 40))).astype(np.uint64)
@@ -418,7 +419,7 @@ def test_autotune_single_range_and_batch(gpu, oracle_mod, sv_mod):
     lo, hi = 10**9, 10**9 + 2 * 10**8
     try:
         t, ms = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi])
-        assert ms > 0 and t["seg_bits"] in (1 << 17, 1 << 18, 1 << 19, 1 << 20)
+        assert ms > 0 and t["seg_bits"] in (1 << 17, 1 << 18, 1 << 19, 622592)
         assert t["block_threads"] in (512, 1024) and t["dense_limit"] >= 37
         assert gpu.tuning()["seg_bits"] == t["seg_bits"]
         t2, ms2 = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi], apply=False)
