@@ -15,29 +15,33 @@ struct Mont {
     uint64_t one;   // R mod n
 };
 
-__device__ __forceinline__ uint64_t mul_hi(uint64_t a, uint64_t b)
+// a * b as a 128-bit (lo, hi) pair from 32-bit limbs: four 32 x 32 + 64
+// multiply-adds, each partial product formed once.
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi)
 {
-    return __umul64hi(a, b);
+    const uint32_t a0 = static_cast<uint32_t>(a), a1 = static_cast<uint32_t>(a >> 32);
+    const uint32_t b0 = static_cast<uint32_t>(b), b1 = static_cast<uint32_t>(b >> 32);
+    const uint64_t p00 = static_cast<uint64_t>(a0) * b0;
+    const uint64_t t1 = static_cast<uint64_t>(a0) * b1 + (p00 >> 32);
+    const uint64_t t2 = static_cast<uint64_t>(a1) * b0 + static_cast<uint32_t>(t1);
+    hi = static_cast<uint64_t>(a1) * b1 + (t1 >> 32) + (t2 >> 32);
+    lo = (t2 << 32) | static_cast<uint32_t>(p00);
 }
 
 // a * b * R^-1 mod n, for a, b < n.
 __device__ __forceinline__ uint64_t mont_mul(const Mont &m, uint64_t a, uint64_t b)
 {
-    const uint64_t t_lo = a * b;
-    const uint64_t t_hi = mul_hi(a, b);
-    const uint64_t q = t_lo * m.ninv;            // t + q*n = 0 mod R
-    const uint64_t qn_hi = mul_hi(q, m.n);
-    // (t + q*n) / R = t_hi + qn_hi + carry out of t_lo + q*n_lo (which is
-    // 0 mod R, so the carry is 1 exactly when t_lo != 0)
-    const uint64_t carry = t_lo != 0 ? 1 : 0;
-    uint64_t r = t_hi + qn_hi;
-    const bool ovf = r < t_hi;
-    const uint64_t r2 = r + carry;
-    const bool ovf2 = r2 < r;
-    r = r2;
-    if (ovf || ovf2 || r >= m.n)
-        r -= m.n;
-    return r;
+    uint64_t t_lo, t_hi, qn_lo, qn_hi;
+    mul_wide(a, b, t_lo, t_hi);
+    const uint64_t q = t_lo * m.ninv;  // t + q*n = 0 mod R
+    mul_wide(q, m.n, qn_lo, qn_hi);    // only the high half is used
+    // (t + q*n) / R = t_hi + qn_hi + (carry out of t_lo + qn_lo, which is 1
+    // exactly when t_lo != 0 since the low halves sum to 0 mod R); it is
+    // below 2n, so n comes off once when the sum passed 2^64 or reached n
+    unsigned long long c1 = 0, c2 = 0;
+    const uint64_t r = __builtin_addcll(t_hi, qn_hi, t_lo != 0 ? 1ull : 0ull, &c1);
+    const uint64_t d = __builtin_subcll(r, m.n, 0ull, &c2);
+    return (c1 | (c2 ^ 1ull)) ? d : r;
 }
 
 __device__ __forceinline__ Mont mont_setup(uint64_t n)
