@@ -67,9 +67,11 @@ typedef struct sieve_ctx sieve_ctx;
  *   seg_bits      odd integers per LDS segment (a multiple of 4096, at most
  *                 622,592 = 19,456 words, the most that two workgroups per
  *                 CU can each hold).  Automatic: a power of two giving about
- *                 two segments per workgroup slot, at most 2^19; ranges of
- *                 at least four rounds of 2^19-bit segments (8 per CU) that
- *                 use no hit buckets take 622,592.
+ *                 two segments per workgroup slot, at most 2^19.  Without hit
+ *                 buckets, a range of at least four rounds of 2^19-bit
+ *                 segments (8 per CU) takes 622,592, and one of two to four
+ *                 rounds takes the smallest multiple of 4096 that still needs
+ *                 only that many rounds (every round full).
  *   dense_limit   base primes below this are marked by a whole wavefront per
  *                 prime (each lane on four residue classes of the multiples);
  *                 primes at or above it by one lane per prime.  Clamped to
@@ -86,7 +88,7 @@ typedef struct sieve_ctx sieve_ctx;
  *                 detected and the call is redone with twice the depth, so
  *                 results never depend on it.
  *   block_threads threads per workgroup: 256, 512 or 1024 (automatic: 1024
- *                 from 2^19-bit segments, 512 from 2^14, else 256).
+ *                 above 2^18-bit segments, 512 from 2^14, else 256).
  *   wg_per_cu     resident workgroups per compute unit for persistent
  *                 launches (0 = as many as LDS allows). */
 typedef struct sieve_tuning {

@@ -59,11 +59,12 @@ int validate_tuning(const sieve_tuning &t, uint32_t lds_bytes)
 }
 
 // Workgroup size for a segment of sw words: more waves share a larger
-// segment's marking work (measured best: 1024 threads from 2^19 bits, 512
-// from 2^14, 256 below).
+// segment's marking work (measured best: 1024 threads for 2^19 bits, 512
+// from 2^14 to 2^18, 256 below).  Above 2^18 bits only two workgroups fit
+// per CU, so they take 1024 threads to keep 32 wavefronts.
 uint32_t default_threads(uint32_t sw)
 {
-    return sw >= 16384 ? 1024u : (sw >= 512 ? 512u : 256u);
+    return sw > 8192 ? 1024u : (sw >= 512 ? 512u : 256u);
 }
 
 // Primes below the dense limit are marked a wavefront per prime: seg_bits /
@@ -118,8 +119,21 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         const bool buckets = t.bucket_limit != 0xffffffffu &&
                              (t.bucket_limit ? true : 2 * p.sqrt_bound >= 3 * sb && p.nbits >= (1ull << 30));
         const uint64_t n_pow2 = (p.n_words + sw - 1) / sw;
-        if (!buckets && n_pow2 >= 8ull * n_cu)
+        const uint64_t slots = 2ull * n_cu;  // two 1024-thread workgroups per CU
+        if (!buckets && n_pow2 >= 4 * slots) {
             sw = kWideSegWords;
+        } else if (!buckets && n_pow2 > slots) {
+            // two to four rounds: the same number of rounds, all of them
+            // full, from the smallest segment that still fits them.  Just
+            // past a full round (513 segments of 2^19 bits) the last round
+            // would hold one segment; at [2, 1e9) (954 -> 1018 segments) the
+            // gain is within noise.
+            const uint64_t rounds = (n_pow2 + slots - 1) / slots;
+            uint64_t bal = (p.n_words + rounds * slots - 1) / (rounds * slots);
+            bal = (bal + kSegGranuleWords - 1) / kSegGranuleWords * kSegGranuleWords;
+            if (bal < sw)
+                sw = static_cast<uint32_t>(bal);
+        }
     }
     p.seg_bits = sw * 32;
     p.dense_limit = t.dense_limit ? t.dense_limit : default_dense_limit(p.seg_bits);

@@ -75,10 +75,20 @@ def test_plan_tuning_resolution():
     # are wanted; smaller segments take fewer threads
     p = sv.sieve_plan(2, 10**10)
     assert p["seg_bits"] == 622592 and p["block_threads"] == 1024 and p["dense_limit"] == 1216
-    p = sv.sieve_plan(2, 10**9)  # 954 segments of 2^19 bits: under four rounds
-    assert p["seg_bits"] == 1 << 19 and p["block_threads"] == 1024 and p["dense_limit"] == 1024
+    # 954 segments of 2^19 bits are two rounds of 512 workgroups, the second
+    # 86% full: the smallest segment that still needs two rounds fills both
+    p = sv.sieve_plan(2, 10**9)
+    assert p["seg_bits"] == 15360 * 32 and p["n_segments"] == 1018 and p["block_threads"] == 1024
+    assert p["dense_limit"] == 960
     assert sv.sieve_plan(0, 2 * 2048 * 2**19)["seg_bits"] == 622592         # exactly 2048 segments
-    assert sv.sieve_plan(0, 2 * 2047 * 2**19)["seg_bits"] == 1 << 19       # 2047 segments
+    q = sv.sieve_plan(0, 2 * 2047 * 2**19)                                  # 2047: four rounds, full
+    assert q["seg_bits"] == 1 << 19 and q["n_segments"] == 2047
+    q = sv.sieve_plan(0, 2 * 1025 * 2**19)                                  # 1025: three rounds
+    assert q["n_segments"] <= 3 * 512 and q["seg_bits"] < 1 << 19 and q["seg_bits"] % 4096 == 0
+    assert q["n_segments"] * q["seg_bits"] >= q["nbits"] and q["block_threads"] == 1024
+    q = sv.sieve_plan(0, 2 * 513 * 2**19)                                   # 513: two rounds of about half
+    assert q["n_segments"] <= 1024 and q["seg_bits"] <= (1 << 18) + 4096 and q["block_threads"] == 1024
+    assert sv.sieve_plan(0, 2 * 512 * 2**19)["seg_bits"] == 1 << 19        # one full round stays
     assert sv.sieve_plan(2, 10**10, n_cu=64)["seg_bits"] == 622592
     # a device with 64 KiB of LDS per workgroup holds 2^18-bit segments at most
     assert sv.sieve_plan(2, 10**10, lds_bytes=65536)["seg_bits"] == 1 << 18
