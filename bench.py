@@ -97,7 +97,14 @@ def host_info(threads):
                     break
     except OSError:
         pass
-    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "threads": threads}
+    mhz = []
+    try:
+        with open("/proc/cpuinfo") as f:
+            mhz = [float(line.split(":", 1)[1]) for line in f if line.startswith("cpu MHz")]
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "threads": threads,
+            "cpu_mhz_mean": round(sum(mhz) / len(mhz), 1) if mhz else None}
 
 
 # Odd primes the segment kernels strike with periodic pre-sieve tables instead
@@ -331,26 +338,30 @@ def run_mr(sv, torch, steps, warmup, n=1 << 24):
                                                          "called one by one from Python"}}
 
 
-def cpu_baseline(lo, hi, expect_pi):
-    """The oracle's count of the whole range on every host thread, and on one
-    thread over the range's last tenth (its densest part)."""
+def cpu_baseline(lo, hi, expect_pi, bitmap=False):
+    """The oracle on the whole range on every host thread, and on one thread
+    over the range's last tenth (its densest part): the count, or with bitmap
+    the packed words and the count, as the GPU leg produces them."""
     import oracle  # CPU-baseline leg only
 
     oracle.build(force=False)
     threads = oracle.default_threads()
+    run = (lambda a, b, t: oracle.bitmap(a, b, threads=t)[1]) if bitmap else \
+          (lambda a, b, t: oracle.count(a, b, threads=t))
+    what = "bitmap and count" if bitmap else "count"
     t0 = time.perf_counter()
-    pi = oracle.count(lo, hi, threads=threads)
+    pi = run(lo, hi, threads)
     dt = time.perf_counter() - t0
     assert pi == expect_pi, (pi, expect_pi)
     lo1 = hi - (hi - lo) // 10
     t1 = time.perf_counter()
-    oracle.count(lo1, hi, threads=1)
+    run(lo1, hi, 1)
     dt1 = time.perf_counter() - t1
     return {"value": (hi - lo) / dt, "unit": "ints/s", "cores": threads, "kind": "oracle",
-            "sample": f"the whole workload: oracle count of [{lo}, {hi}) on {threads} threads, "
+            "sample": f"the whole workload: oracle {what} of [{lo}, {hi}) on {threads} threads, "
                       f"{dt:.2f} s, pi={pi}",
             "one_thread": {"value": (hi - lo1) / dt1, "unit": "ints/s", "cores": 1,
-                           "sample": f"oracle count of [{lo1}, {hi}) on one thread, {dt1:.2f} s"},
+                           "sample": f"oracle {what} of [{lo1}, {hi}) on one thread, {dt1:.2f} s"},
             "host": host_info(threads)}
 
 
@@ -484,10 +495,12 @@ def main():
     for _ in range(args.warmup):
         assert step() == wl["pi"]
     torch.cuda.synchronize()
-    kernel_ms = []
+    kernel_ms, call_ms = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        tc = time.perf_counter()
         pi = step()
+        call_ms.append(1e3 * (time.perf_counter() - tc))
         kernel_ms.append(sv.sieve_last_kernel_ms(s.ctx))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -520,6 +533,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "cold_ms": cold_ms,
+        "call_ms": {"p50": float(np.percentile(call_ms, 50)), "min": float(np.min(call_ms)),
+                    "max": float(np.max(call_ms))},
         "device": device,
         "config": {"workload": wl["name"], "lo": lo, "hi": hi, "pi": pi,
                    "presieve_primes": PRESIEVE_PRIMES,
@@ -534,7 +549,7 @@ def main():
         rec["serve"] = run_serve(sv, args.serve_seconds or 5.0)
         rec["mr"] = run_mr(sv, torch, steps=3, warmup=1)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"])
+        rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"], bitmap=wl["bitmap"])
         if "batch" in rec:
             rec["batch"]["cpu_baseline"] = batch_cpu_baseline(sv, rec["batch"]["_pi"])
     if "batch" in rec:
