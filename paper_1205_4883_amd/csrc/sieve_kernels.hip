@@ -256,48 +256,51 @@ __device__ __forceinline__ void mark_dense(uint32_t *seg, uint32_t sw, uint32_t 
 
 // Sparse marking of one prime by one lane: the multiples p*m with m prime to
 // 15 from bit offset o (whose multiplier sits at wheel position idx) up to
-// lim_bits.  The eight offsets of one turn of the wheel (15 odd steps, 15p
-// bits) are computed once, so a mark inside a full turn costs one add plus
-// the address and mask; the last partial turn is guarded mark by mark.
-// Returns the offset of the first multiple left unmarked (at or past
-// lim_bits) and sets idx to its wheel position, so that the next segment
-// can continue from there.
+// lim_bits.  While a whole turn of the wheel (15 odd steps, 15p bits, 8
+// marks) fits, the eight offsets of a turn are computed once and a mark costs
+// one add plus the address and mask; only lanes whose prime is small enough
+// build them, so a wavefront of large primes (a few marks per segment, the
+// common case in batches near 1e12) skips the table.  The rest of the last
+// turn is walked mark by mark along the rotated gaps.  Returns the offset of
+// the first multiple left unmarked (at or past lim_bits) and sets idx to its
+// wheel position, so that the next segment can continue from there.
 // kSmall: p < 2^24, so the offsets are full-rate 24-bit products.
 template <bool kSmall>
 __device__ __forceinline__ uint32_t mark_wheel(uint32_t *seg, uint32_t lim_bits, uint32_t p, uint32_t o,
                                                uint32_t &idx)
 {
     const uint32_t g = __builtin_amdgcn_alignbit(kWheelGaps, kWheelGaps, 2 * idx);
-    uint32_t d[8];
-    d[0] = 0;
-    uint32_t cum = 0;  // odd steps from the turn's first multiple
-#pragma unroll
-    for (int j = 1; j < 8; ++j) {
-        cum += (g >> (2 * (j - 1))) & 3u;
-        d[j] = kSmall ? __umul24(cum, p) : cum * p;
-    }
-    const uint32_t turn = kSmall ? __umul24(15u, p) : 15 * p;
     uint32_t base = o;
-    for (; base + d[7] < lim_bits; base += turn) {
+    // the seven offsets after a turn's first multiple are at most 14p
+    if (base + (kSmall ? __umul24(14u, p) : 14 * p) < lim_bits) {
+        uint32_t d[8];
+        d[0] = 0;
+        uint32_t cum = 0;  // odd steps from the turn's first multiple
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t x = base + d[j];
-            lds_or(seg + (x >> 5), 1u << (x & 31));
+        for (int j = 1; j < 8; ++j) {
+            cum += (g >> (2 * (j - 1))) & 3u;
+            d[j] = kSmall ? __umul24(cum, p) : cum * p;
         }
-    }
-    uint32_t next = base + d[7], step = 7;
+        const uint32_t turn = kSmall ? __umul24(15u, p) : 15 * p;
+        do {
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        const uint32_t x = base + d[j];
-        if (x >= lim_bits) {
-            next = x;
-            step = j;
-            break;
-        }
-        lds_or(seg + (x >> 5), 1u << (x & 31));
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t x = base + d[j];
+                lds_or(seg + (x >> 5), 1u << (x & 31));
+            }
+            base += turn;
+        } while (base + d[7] < lim_bits);
     }
-    idx = (idx + step) & 7u;
-    return next;
+    // at most one turn is left: base sits at wheel position idx again
+    uint32_t s = 0;
+    while (base < lim_bits) {
+        lds_or(seg + (base >> 5), 1u << (base & 31));
+        const uint32_t gap = (g >> (2 * s)) & 3u;
+        base += kSmall ? __umul24(gap, p) : gap * p;
+        ++s;
+    }
+    idx = (idx + s) & 7u;
+    return base;
 }
 
 // The first word of a range: 1 is not prime; 3..31 are primes that the
