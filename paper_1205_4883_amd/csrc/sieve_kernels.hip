@@ -25,9 +25,12 @@
 // leaves 1 unmarked, which the first word of a range corrects.
 //
 // LDS bank behaviour on gfx950 (32 banks of 4 bytes; each 32-lane half of a
-// wave is served separately) sets the cost of the scattered atomic ORs; the
-// wheel cuts their number, and the fixed-bit lane layout keeps the VALU work
-// per dense mark at one add.
+// wave is served separately) sets the cost of the scattered atomic ORs.  The
+// wheel cuts their number; the fixed-bit lane layout keeps the VALU work per
+// dense mark at one add, and a per-prime choice of which classes share a
+// half-wavefront spreads the dense marks over the banks.  A segment holds up
+// to 19,456 words, the most with which two 1024-thread workgroups still fit
+// in a CU's 160 KiB of LDS.
 #include <atomic>
 
 #include "dense_layout.h"
