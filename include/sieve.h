@@ -185,9 +185,12 @@ SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64
 
 /* The odd-only prime bitmap of [lo, hi) (steps A1-A8) written to the DEVICE
  * buffer d_words[0 .. n_words); words past sieve_bitmap_words(lo, hi) are not
- * touched.  d_words must be 4-byte aligned.  With pi_out == NULL the call is
- * asynchronous (ordered on `stream`); otherwise it synchronises `stream`, so
- * the words are written when it returns, and stores pi.
+ * touched.  d_words must be 4-byte aligned.  The words are written in
+ * stream order: later work on `stream` (a copy, a kernel, torch operations on
+ * that stream) sees them; synchronise `stream` before reading them any other
+ * way.  With pi_out == NULL the call returns at once; otherwise it returns
+ * as soon as the launch's last workgroup has published pi to pinned host
+ * memory (without synchronising `stream`) and stores it.
  * Errors: SIEVE_EINVAL (ctx NULL, d_words NULL with a non-empty range,
  * misaligned d_words, lo > hi), SIEVE_ERANGE, SIEVE_EBUFSZ (n_words too
  * small), SIEVE_ENOMEM, SIEVE_EDEVICE. */

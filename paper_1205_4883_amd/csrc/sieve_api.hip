@@ -565,16 +565,11 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
                                &si))
         return st;
     if (pi_out) {
+        // the count is known once published; a bitmap's words follow in
+        // stream order like any launch on s
         uint64_t v = kUnpublished;
-        if (d_words) {
-            // a bitmap call returns with the words written
-            HIP_TRY(c, hipStreamSynchronize(s));
-            v = *published(c);
-            if (v == kUnpublished)
-                return SIEVE_EDEVICE;
-        } else if (int st = wait_published(c, si, s, &v)) {
+        if (int st = wait_published(c, si, s, &v))
             return st;
-        }
         *pi_out = v + two;
     }
     return SIEVE_OK;
