@@ -225,11 +225,13 @@ SIEVE_API int sieve_batch(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, 
 
 /* Batched primality of 64-bit integers (the paper's Section 3.2): out[i] = 1
  * when n[i] is prime.  Deterministic Miller-Rabin (the test the paper points
- * to), with the first k primes as bases for the published bounds below which
- * they admit no strong pseudoprime, k <= 12 for every n < 2^64; the modular
- * powers are Alg. 2's repeated squaring in Montgomery form.  d_n and d_out
- * are DEVICE arrays of count entries (uint64, uint8).  Asynchronous on
- * `stream`; sieve_last_kernel_ms times it (timing on).  Errors: SIEVE_EINVAL (NULL
+ * to): below 341,550,071,728,321 the bases are the first k <= 7 primes, from
+ * the published bounds below which they admit no strong pseudoprime; above
+ * it the seven bases 2, 325, 9375, 28178, 450775, 9780504, 1795265022, which
+ * admit none below 2^64.  The modular powers are repeated squaring (Alg. 2)
+ * in Montgomery form, taken from the top bit down.  d_n and d_out are DEVICE
+ * arrays of count entries (uint64, uint8).  Asynchronous on `stream`;
+ * sieve_last_kernel_ms times it (timing on).  Errors: SIEVE_EINVAL (NULL
  * arrays), SIEVE_EDEVICE. */
 SIEVE_API int sieve_is_prime_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, uint8_t *d_out,
                                    void *stream);
