@@ -339,22 +339,46 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 
 constexpr uint32_t kNoItem = 0xffffffffu;
 
-// Thread 0's pop from a launch's spread work queues: the next item below
-// n_items, or kNoItem once every queue is dry.  q is the workgroup's current
-// queue and dry the number of queues it has found empty (a queue never
-// refills, so dry only grows and the workgroup leaves after kQueues failed
-// pops).
-__device__ __forceinline__ uint32_t pop_item(uint32_t *counters, uint32_t &q, uint32_t &dry, uint32_t n_items)
+// The next work item of a launch, for thread 0 of a workgroup.  An atomic
+// add on queue q's counter hands out items q, q + kQueues, q + 2 kQueues, ...
+// Once q runs dry, all the counters are read together (independent loads,
+// one round trip) and the pop moves to a queue that still has items, rather
+// than trying each queue in turn with an atomic of its own (eight serial
+// device-scope round trips at the end of every workgroup).  Counters only
+// grow, so each failed pop retires a queue and the loop ends.  Returns
+// kNoItem when every queue is dry.
+__device__ __forceinline__ uint32_t pop_item(uint32_t *counters, uint32_t &q, uint32_t n_items)
 {
-    while (dry < kQueues) {
+    for (;;) {
         const uint32_t k = atomicAdd(counters + q * kLineWords, 1u);
         const uint64_t item = static_cast<uint64_t>(k) * kQueues + q;
         if (item < n_items)
             return static_cast<uint32_t>(item);
-        ++dry;
-        q = q + 1 == kQueues ? 0 : q + 1;
+        uint32_t seen[kQueues];
+#pragma unroll
+        for (uint32_t j = 0; j < kQueues; ++j)
+            seen[j] = __hip_atomic_load(counters + j * kLineWords, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t next = kQueues;
+#pragma unroll
+        for (uint32_t d = kQueues - 1; d >= 1; --d) {  // nearest after q wins
+            const uint32_t j = (q + d) % kQueues;
+            if (static_cast<uint64_t>(seen[j]) * kQueues + j < n_items)
+                next = j;
+        }
+        if (next == kQueues)
+            return kNoItem;
+        q = next;
     }
-    return kNoItem;
+}
+
+// Work item for thread 0 of workgroup b on its pass `pass` (0, 1, ...):
+// with no more items than workgroups each takes item b once, with no queue
+// at all; otherwise pop_item.
+__device__ __forceinline__ uint32_t next_item(uint32_t *counters, uint32_t &q, uint32_t n_items, uint32_t pass)
+{
+    if (n_items <= gridDim.x)
+        return pass == 0 && blockIdx.x < n_items ? blockIdx.x : kNoItem;
+    return pop_item(counters, q, n_items);
 }
 
 // Sum of every thread's v over the workgroup, valid in thread 0 (red: one
@@ -640,13 +664,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     const uint32_t n_items = n_chunks + (n_segments - n_chunks * chunk);
     const uint32_t carry_end = min(pa.n_primes, pa.n_dense + kCarry * blockDim.x);
     const bool small = small_primes(pa.primes, pa.n_primes);
-    uint32_t q = blockIdx.x % kQueues, dry = 0;
+    uint32_t q = blockIdx.x % kQueues;
     unsigned long long acc = 0;
     uint32_t carry[kCarry];
-    for (;;) {
+    for (uint32_t pass = 0;; ++pass) {
         __syncthreads();  // tables built / the previous segment's LDS is free
         if (t == 0)
-            item_sh = pop_item(r.counters, q, dry, n_items);
+            item_sh = next_item(r.counters, q, n_items, pass);
         __syncthreads();
         const uint32_t item = item_sh;
         if (item == kNoItem)
@@ -698,9 +722,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     uint32_t *counters = reinterpret_cast<uint32_t *>(blob + kBlobCounterOff);
     const BatchInterval *ivs = reinterpret_cast<const BatchInterval *>(blob + hdr->iv_off);
     const uint32_t *item_iv = reinterpret_cast<const uint32_t *>(blob + hdr->item_off);
-    uint32_t q = blockIdx.x % kQueues, dry = 0;
+    uint32_t q = blockIdx.x % kQueues;
     uint32_t prev = kNoItem;
-    for (;;) {
+    for (uint32_t pass = 0;; ++pass) {
         __syncthreads();  // red[] holds the previous item's wave counts; LDS is free
         if (threadIdx.x == 0) {
             if (prev != kNoItem) {
@@ -709,7 +733,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                     total += red[w];
                 item_counts[prev] = total;
             }
-            item_sh = pop_item(counters, q, dry, n_items);
+            item_sh = next_item(counters, q, n_items, pass);
         }
         __syncthreads();
         const uint32_t item = item_sh;
