@@ -244,8 +244,10 @@ SIEVE_API int sieve_is_prime_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t
 SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, const uint64_t *d_draws,
                                  uint32_t iterations, uint8_t *d_out, void *stream);
 
-/* Autotuner.  Times candidate tunings (segment size with a matching
- * workgroup size, and the dense/sparse bound) on the given work - one
+/* Autotuner.  Times candidate tunings (the automatic plan, then segment
+ * sizes with a matching workgroup size times three dense/sparse bounds) on
+ * the given work, so the answer is never slower than the untuned context -
+ * one
  * interval is timed as sieve_range_count, several as a count-only
  * sieve_batch - and returns the fastest in *best (and its kernel time in
  * *best_ms if not NULL).  Results are cached per context by (single range

@@ -1163,22 +1163,24 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             c->tuning = *best;
         return SIEVE_OK;
     }
-    // Segment sizes with the workgroup size measured best for each on the
-    // count of [2, 10^10), times three dense/sparse bounds.
+    // The automatic plan first (so the answer is never slower than what the
+    // context does untuned), then segment sizes with the workgroup size
+    // measured best for each on the count of [2, 10^10), times three
+    // dense/sparse bounds.
     struct SegChoice {
         uint32_t seg_bits, threads;
     };
     const SegChoice segs[] = {{1u << 17, 512}, {1u << 18, 512}, {1u << 19, 1024}, {sv::kWideSegWords * 32, 1024}};
     const uint32_t dense_div[] = {1024, 512, 256};
     const sieve_tuning saved = c->tuning;
-    const bool saved_timing = c->timing;
-    c->timing = true;  // candidates are ranked by their kernel times
-    std::vector<sieve_interval> count_only(iv, iv + n);
-    for (auto &v : count_only)
-        v.flags = 0;
-    sieve_tuning win{};
-    double win_ms = 1e300;
-    int st = SIEVE_OK;
+    std::vector<sieve_tuning> cands;
+    {
+        sieve_tuning t = saved;
+        t.seg_bits = 0;
+        t.block_threads = 0;
+        t.dense_limit = 0;
+        cands.push_back(t);
+    }
     for (const SegChoice &sc : segs) {
         if (sc.seg_bits / 32 > sv::max_seg_words(c->lds_max))
             continue;
@@ -1187,29 +1189,38 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             t.seg_bits = sc.seg_bits;
             t.block_threads = sc.threads;
             t.dense_limit = std::max(sc.seg_bits / dd, sv::kFirstMarkedPrime);
-            c->tuning = t;
-            double ms = 1e300;
-            for (int rep = 0; rep < 3 && st == SIEVE_OK; ++rep) {
-                if (n == 1) {
-                    uint64_t pi = 0;
-                    st = sv::run_range(c, iv[0].lo, iv[0].hi, nullptr, &pi, c->stream);
-                } else {
-                    std::vector<uint64_t> pi(n);
-                    st = sieve_batch(c, count_only.data(), n, nullptr, 0, pi.data(), nullptr);
-                }
-                double k = 0;
-                if (st == SIEVE_OK && rep > 0 && sieve_last_kernel_ms(c, &k) == SIEVE_OK)
-                    ms = std::min(ms, k);  // the first run is a warm-up
+            cands.push_back(t);
+        }
+    }
+    const bool saved_timing = c->timing;
+    c->timing = true;  // candidates are ranked by their kernel times
+    std::vector<sieve_interval> count_only(iv, iv + n);
+    for (auto &v : count_only)
+        v.flags = 0;
+    sieve_tuning win{};
+    double win_ms = 1e300;
+    int st = SIEVE_OK;
+    for (const sieve_tuning &t : cands) {
+        c->tuning = t;
+        double ms = 1e300;
+        for (int rep = 0; rep < 3 && st == SIEVE_OK; ++rep) {
+            if (n == 1) {
+                uint64_t pi = 0;
+                st = sv::run_range(c, iv[0].lo, iv[0].hi, nullptr, &pi, c->stream);
+            } else {
+                std::vector<uint64_t> pi(n);
+                st = sieve_batch(c, count_only.data(), n, nullptr, 0, pi.data(), nullptr);
             }
-            if (st != SIEVE_OK)
-                break;
-            if (ms < win_ms) {
-                win_ms = ms;
-                win = t;
-            }
+            double k = 0;
+            if (st == SIEVE_OK && rep > 0 && sieve_last_kernel_ms(c, &k) == SIEVE_OK)
+                ms = std::min(ms, k);  // the first run is a warm-up
         }
         if (st != SIEVE_OK)
             break;
+        if (ms < win_ms) {
+            win_ms = ms;
+            win = t;
+        }
     }
     c->tuning = saved;
     c->timing = saved_timing;
