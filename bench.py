@@ -410,6 +410,8 @@ def main():
     ap.add_argument("--seg-bits", type=int, default=0, help="tuning: odd integers per segment")
     ap.add_argument("--dense-limit", type=int, default=0, help="tuning: wave-per-prime bound")
     ap.add_argument("--block-threads", type=int, default=0, help="tuning: threads per workgroup")
+    ap.add_argument("--bucket-limit", type=int, default=0,
+                    help="tuning: primes from here on go through hit buckets (0 automatic, 4294967295 never)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -459,9 +461,9 @@ def main():
     if args.workload == "batch-4096":
         s = sv.Sieve(0)
         sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
-        if args.seg_bits or args.dense_limit or args.block_threads:
+        if args.seg_bits or args.dense_limit or args.block_threads or args.bucket_limit:
             s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
-                     block_threads=args.block_threads)
+                     block_threads=args.block_threads, bucket_limit=args.bucket_limit)
         b = run_batch(sv, torch, s, args.steps, args.warmup, check_plain=not args.no_plain)
         s.close()
         pi = b.pop("_pi")
@@ -478,8 +480,9 @@ def main():
     lo, hi = wl["lo"], wl["hi"]
     s = sv.Sieve(0)
     sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
-    if args.seg_bits or args.dense_limit or args.block_threads:
-        s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads)
+    if args.seg_bits or args.dense_limit or args.block_threads or args.bucket_limit:
+        s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads,
+                 bucket_limit=args.bucket_limit)
     stream = torch.cuda.current_stream(0)
     out = s.alloc_words(lo, hi) if wl["bitmap"] else None
 
