@@ -246,8 +246,10 @@ SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t c
 
 /* Autotuner.  Times candidate tunings (the automatic plan, then segment
  * sizes with a matching workgroup size times three dense/sparse bounds) on
- * the given work, so the answer is never slower than the untuned context -
- * one
+ * the given work, so the answer is never slower than the untuned context,
+ * then refines the winner: one or two resident workgroups per CU and, for a
+ * single range that uses hit buckets, a large-prime threshold of 2x or 4x
+ * the segment size or no buckets - one
  * interval is timed as sieve_range_count, several as a count-only
  * sieve_batch - and returns the fastest in *best (and its kernel time in
  * *best_ms if not NULL).  Results are cached per context by (single range

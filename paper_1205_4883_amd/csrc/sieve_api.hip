@@ -1200,7 +1200,7 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
     sieve_tuning win{};
     double win_ms = 1e300;
     int st = SIEVE_OK;
-    for (const sieve_tuning &t : cands) {
+    auto time_it = [&](const sieve_tuning &t) {
         c->tuning = t;
         double ms = 1e300;
         for (int rep = 0; rep < 3 && st == SIEVE_OK; ++rep) {
@@ -1215,12 +1215,42 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             if (st == SIEVE_OK && rep > 0 && sieve_last_kernel_ms(c, &k) == SIEVE_OK)
                 ms = std::min(ms, k);  // the first run is a warm-up
         }
-        if (st != SIEVE_OK)
-            break;
-        if (ms < win_ms) {
+        if (st == SIEVE_OK && ms < win_ms) {
             win_ms = ms;
             win = t;
         }
+    };
+    for (const sieve_tuning &t : cands) {
+        time_it(t);
+        if (st != SIEVE_OK)
+            break;
+    }
+    // Refine the winner: fewer resident workgroups per CU, and for a single
+    // range that uses hit buckets, a higher large-prime threshold or none.
+    std::vector<sieve_tuning> refine;
+    if (st == SIEVE_OK) {
+        for (uint32_t w : {1u, 2u}) {
+            sieve_tuning t = win;
+            t.wg_per_cu = w;
+            refine.push_back(t);
+        }
+        sieve_plan_info pl{};
+        if (n == 1 && sv::make_plan(iv[0].lo, iv[0].hi, &win, c->n_cu, c->lds_max, &pl) == SIEVE_OK &&
+            pl.bucket_limit) {
+            for (uint32_t f : {2u, 4u}) {
+                sieve_tuning t = win;
+                t.bucket_limit = static_cast<uint32_t>(std::min<uint64_t>(uint64_t(f) * pl.seg_bits, 0xfffffffeull));
+                refine.push_back(t);
+            }
+            sieve_tuning t = win;
+            t.bucket_limit = 0xffffffffu;  // never
+            refine.push_back(t);
+        }
+    }
+    for (const sieve_tuning &t : refine) {
+        time_it(t);
+        if (st != SIEVE_OK)
+            break;
     }
     c->tuning = saved;
     c->timing = saved_timing;

@@ -419,12 +419,14 @@ def test_autotune_single_range_and_batch(gpu, oracle_mod, sv_mod):
     lo, hi = 10**9, 10**9 + 2 * 10**8
     try:
         t, ms = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi])
-        # the automatic plan (zero fields) is one of the candidates
+        # the automatic plan (zero fields) is one of the candidates; the
+        # refinement may then cap the workgroups per CU
         assert ms > 0 and t["seg_bits"] in (0, 1 << 17, 1 << 18, 1 << 19, 622592)
         if t["seg_bits"]:
             assert t["block_threads"] in (512, 1024) and t["dense_limit"] >= 37
         else:
             assert t["block_threads"] == 0 and t["dense_limit"] == 0
+        assert t["wg_per_cu"] in (0, 1, 2)
         assert gpu.tuning()["seg_bits"] == t["seg_bits"]
         t2, ms2 = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi], apply=False)
         assert t2 == t and ms2 == ms  # cache hit
@@ -437,7 +439,27 @@ def test_autotune_single_range_and_batch(gpu, oracle_mod, sv_mod):
         for i in range(len(los)):
             assert int(pi[i]) == oracle_mod.count(int(los[i]), int(his[i])), (tb, i)
     finally:
-        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0)
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0, wg_per_cu=0, bucket_limit=0)
+
+
+def test_autotune_bucketed_range(gpu, oracle_mod, sv_mod):
+    # high in the domain the automatic plan uses hit buckets, so the tuner
+    # also times larger large-prime thresholds and no buckets at all
+    lo, hi = 10**13, 10**13 + 2**31
+    try:
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0, wg_per_cu=0, bucket_limit=0)
+        assert sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())["bucket_limit"] > 0
+        t, ms = sv_mod.sieve_autotune(gpu.ctx, [lo], [hi])
+        assert ms > 0 and t["wg_per_cu"] in (0, 1, 2)
+        plan = sv_mod.sieve_plan(lo, hi, tuning=t)
+        if t["bucket_limit"] not in (0, 0xFFFFFFFF):
+            assert t["bucket_limit"] in (2 * plan["seg_bits"], 4 * plan["seg_bits"])
+        assert gpu.tuning() == t
+        assert gpu.count(lo, hi) == oracle_mod.count(lo, hi)
+        words, pi = gpu.bitmap(lo, lo + 3 * 10**7 + 11)
+        assert pi == oracle_mod.count(lo, lo + 3 * 10**7 + 11)
+    finally:
+        gpu.tuning(seg_bits=0, dense_limit=0, block_threads=0, wg_per_cu=0, bucket_limit=0)
 
 
 # -- large-prime hit buckets ---------------------------------------------------
