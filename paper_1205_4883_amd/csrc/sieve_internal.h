@@ -15,14 +15,15 @@ constexpr uint32_t kFirstMarkedPrime = 37;
 
 // The widest LDS segment, in words: two 1024-thread workgroups with their
 // pre-sieve tables, item word and reduction space still fit in a CU's
-// 160 KiB (2 x (740 + 19456) x 4 B plus under 1 KiB each), so a CU keeps 32
+// 160 KiB (2 x (792 + 19456) x 4 B plus 136 B each), so a CU keeps 32
 // wavefronts while each segment holds 622,592 odd integers (19% more than
 // 2^19, for less per-segment set-up).  Not a power of two, so hit buckets
 // stay with 2^19-bit segments.
 constexpr uint32_t kWideSegWords = 19456;
 // LDS words taken by the three pre-sieve tables (each is its pattern's
-// period plus two spare words, rounded so the segment starts 16-byte aligned).
-constexpr uint32_t kTableWords = 740;
+// period plus one pre-sieve run's words, rounded so the segment starts
+// 16-byte aligned).
+constexpr uint32_t kTableWords = 792;
 // The bootstrap kernel sieves the odd integers below 2^16 in one workgroup.
 constexpr uint32_t kBootstrapLimit = 65536;
 constexpr uint32_t kBootstrapOddPrimes = 6541;  // odd primes below 2^16

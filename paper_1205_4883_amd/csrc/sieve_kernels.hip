@@ -42,11 +42,16 @@ namespace {
 constexpr uint32_t kLA = 3u * 5u * 7u * 11u * 13u;  // 15015
 constexpr uint32_t kLB = 17u * 19u * 23u;           // 7429
 constexpr uint32_t kLC = 29u * 31u;                 // 899
-// A table of period L holds the words k <= (L - 1) / 32 + 2: enough for a
-// 96-bit window (two output words) starting at any phase j < L.
-constexpr uint32_t kWA = (kLA - 1) / 32 + 3;  // 472
-constexpr uint32_t kWB = (kLB - 1) / 32 + 3;  // 235
-constexpr uint32_t kWC = (kLC - 1) / 32 + 3;  // 31
+// The pre-sieve fills a segment in runs of up to kRun consecutive words per
+// thread.  kRun is odd, and so is every run length used, so that the runs of
+// a half-wavefront's 32 lanes start on 32 distinct LDS banks.
+constexpr uint32_t kRun = 19;
+// A table of period L holds the words k <= (L - 1) / 32 + kRun: enough for a
+// run of kRun words starting at any phase j < L (word k of the run is a
+// funnel shift of table words (j >> 5) + k and (j >> 5) + k + 1).
+constexpr uint32_t kWA = (kLA - 1) / 32 + kRun + 1;  // 489
+constexpr uint32_t kWB = (kLB - 1) / 32 + kRun + 1;  // 252
+constexpr uint32_t kWC = (kLC - 1) / 32 + kRun + 1;  // 48
 static_assert(kWA + kWB + kWC <= kTableWords, "pre-sieve tables exceed their LDS area");
 
 // Odd residues r mod 30 prime to 15, as a bit mask.
@@ -121,15 +126,6 @@ __device__ __forceinline__ void build_tables(uint32_t *tabs)
 {
     for (uint32_t k = threadIdx.x; k < kTableWords; k += blockDim.x)
         tabs[k] = kTables.w[k];
-}
-
-// 64 pattern bits starting at phase j of a table, as two words: funnel
-// shifts of three consecutive table words.
-__device__ __forceinline__ uint2 pattern2_at(const uint32_t *tab, uint32_t j)
-{
-    const uint32_t *t = tab + (j >> 5);
-    const uint32_t a = t[0], b = t[1], c = t[2];
-    return make_uint2(__builtin_amdgcn_alignbit(b, a, j), __builtin_amdgcn_alignbit(c, b, j));
 }
 
 // The first odd multiple m0*p of p with m0*p >= n0 and m0 >= p (crossing off
@@ -419,36 +415,55 @@ __device__ __forceinline__ SegGeom seg_geom(uint64_t seg, uint32_t seg_words_max
 }
 
 // 1. pre-sieve.  Bit i of the segment is the odd integer 2x + 1 with
-//    x = (n0 >> 1) + i; pattern phases are x mod L.  Each thread fills two
-//    adjacent words per step (one 64-bit LDS store), so a phase update and
-//    three table reads serve two words.
+//    x = (n0 >> 1) + i; pattern phases are x mod L.  Each thread fills runs
+//    of `run` consecutive words (odd, at most kRun): after the phases of the
+//    run's first word, every further word costs one read and one funnel
+//    shift per table, and a word store.  Consecutive lanes' runs lie `run`
+//    words apart, so the stores of a half-wavefront hit 32 distinct banks.
+//    kFull unrolls the run completely (fastest where registers allow; the
+//    batch kernel, which holds more state per item, takes a shorter unroll
+//    so that nothing spills).
+template <bool kFull>
 __device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg_lds, const SegGeom &g)
 {
-    const uint32_t t = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
-    const uint64_t x0 = (g.n0 >> 1) + 64ull * t;
-    uint32_t ja = static_cast<uint32_t>(x0 % kLA);
-    uint32_t jb = static_cast<uint32_t>(x0 % kLB);
-    uint32_t jc = static_cast<uint32_t>(x0 % kLC);
-    const uint32_t sa = (64u * nthreads) % kLA;
-    const uint32_t sb = (64u * nthreads) % kLB;
-    const uint32_t sc = (64u * nthreads) % kLC;
-    const uint32_t *ta = tabs;
-    const uint32_t *tb = tabs + kWA;
-    const uint32_t *tc = tabs + kWA + kWB;
-    for (uint32_t w = 2 * t; w < g.sw; w += 2 * nthreads) {
-        const uint2 a = pattern2_at(ta, ja), b = pattern2_at(tb, jb), c = pattern2_at(tc, jc);
-        const uint2 v = make_uint2(a.x | b.x | c.x, a.y | b.y | c.y);
-        if (w + 1 < g.sw)
-            *reinterpret_cast<uint2 *>(seg_lds + w) = v;  // w even: 8-byte aligned
-        else
-            seg_lds[w] = v.x;
-        ja += sa;
-        ja = min(ja, ja - kLA);  // unsigned: subtract L once if ja >= L
-        jb += sb;
+    const uint32_t run = min(((g.sw + nthreads - 1) / nthreads) | 1u, kRun);
+    const uint64_t x0 = g.n0 >> 1;
+    const uint32_t ra = static_cast<uint32_t>(x0 % kLA);
+    const uint32_t rb = static_cast<uint32_t>(x0 % kLB);
+    const uint32_t rc = static_cast<uint32_t>(x0 % kLC);
+    for (uint32_t w0 = threadIdx.x * run; w0 < g.sw; w0 += nthreads * run) {
+        // 32 * w0 < 2^20: the phases of word w0, each reduced once
+        uint32_t ja = ra + (32 * w0) % kLA;
+        ja = min(ja, ja - kLA);
+        uint32_t jb = rb + (32 * w0) % kLB;
         jb = min(jb, jb - kLB);
-        jc += sc;
+        uint32_t jc = rc + (32 * w0) % kLC;
         jc = min(jc, jc - kLC);
+        const uint32_t *ta = tabs + (ja >> 5);
+        const uint32_t *tb = tabs + kWA + (jb >> 5);
+        const uint32_t *tc = tabs + kWA + kWB + (jc >> 5);
+        uint32_t *out = seg_lds + w0;
+        uint32_t a = ta[0], b = tb[0], c = tc[0];
+        const uint32_t n = min(run, g.sw - w0);  // the segment's last run may be cut short
+        auto word = [&](uint32_t k) {
+            const uint32_t a1 = ta[k + 1], b1 = tb[k + 1], c1 = tc[k + 1];
+            out[k] = __builtin_amdgcn_alignbit(a1, a, ja) | __builtin_amdgcn_alignbit(b1, b, jb) |
+                     __builtin_amdgcn_alignbit(c1, c, jc);
+            a = a1;
+            b = b1;
+            c = c1;
+        };
+        if (kFull) {
+#pragma unroll
+            for (uint32_t k = 0; k < kRun; ++k)
+                if (k < n)
+                    word(k);
+        } else {
+#pragma unroll 4
+            for (uint32_t k = 0; k < n; ++k)
+                word(k);
+        }
     }
 }
 
@@ -592,7 +607,7 @@ __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint3
                                   uint32_t n_primes, uint32_t *out)
 {
     const SegGeom g = seg_geom(seg, seg_words_max, first_odd, n_words);
-    seg_presieve(tabs, seg_lds, g);
+    seg_presieve<false>(tabs, seg_lds, g);
     __syncthreads();
     seg_dense(seg_lds, g, primes, inv, n_dense);
     seg_sparse<kSmall>(seg_lds, g, primes, inv, n_dense, n_primes);
@@ -682,7 +697,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             if (k)
                 __syncthreads();  // the previous segment's count has read the LDS
             const SegGeom g = seg_geom(first + k, seg_words, r.first_odd, r.n_words);
-            seg_presieve(tabs, seg, g);
+            seg_presieve<true>(tabs, seg, g);
             __syncthreads();
             seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense);
             if (small)
@@ -1002,7 +1017,9 @@ __global__ void __launch_bounds__(256) reciprocal_kernel(const uint32_t *primes,
 
 // Static LDS sizes the segment kernels are built for (words of segment).
 constexpr uint32_t kSegSizes[] = {512, 2048, 8192, 16384, kWideSegWords};
-static_assert(2 * ((kTableWords + kWideSegWords) * 4 + 1024) <= 160 * 1024,
+// (beside the tables and the segment: the item word and the reduction array,
+// 132 bytes, with room for alignment)
+static_assert(2 * ((kTableWords + kWideSegWords) * 4 + 256) <= 160 * 1024,
               "two workgroups of the widest segment per CU");
 
 }  // namespace
