@@ -394,8 +394,10 @@ def batch_cpu_baseline(sv, pi_gpu, n_sample=512):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # enough warm-up for the shader clock to leave its idle level (a cold
+    # [2, 1e10) kernel runs about 6% slower over its first ten launches)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="count-1e10",
                     choices=sorted(WORKLOADS) + ["batch-4096", "serve-2000", "mr-2e24"])
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -546,11 +548,11 @@ def main():
         "roofline": roof,
     }
     if args.workload == "count-1e10" and not args.no_batch:
-        rec["batch"] = run_batch(sv, torch, s, steps=3, warmup=1)
+        rec["batch"] = run_batch(sv, torch, s, steps=20, warmup=5)
     s.close()
     if args.workload == "count-1e10" and not args.no_batch:
         rec["serve"] = run_serve(sv, args.serve_seconds or 5.0)
-        rec["mr"] = run_mr(sv, torch, steps=3, warmup=1)
+        rec["mr"] = run_mr(sv, torch, steps=20, warmup=5)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"], bitmap=wl["bitmap"])
         if "batch" in rec:
