@@ -117,7 +117,7 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         // round.
         const uint64_t sb = static_cast<uint64_t>(sw) * 32;
         const bool buckets = t.bucket_limit != 0xffffffffu &&
-                             (t.bucket_limit ? true : 2 * p.sqrt_bound >= 3 * sb && p.nbits >= (1ull << 30));
+                             (t.bucket_limit ? true : 2 * p.sqrt_bound >= 5 * sb && p.nbits >= (1ull << 30));
         const uint64_t n_pow2 = (p.n_words + sw - 1) / sw;
         const uint64_t slots = 2ull * n_cu;  // two 1024-thread workgroups per CU
         if (!buckets && n_pow2 >= 4 * slots) {
@@ -141,16 +141,19 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
     // Hit buckets need power-of-two segments and only pay when the largest
-    // base primes skip most segments (measured: from sqrt(hi) of about
-    // 1.9 segments on, e.g. 2.30 -> 1.99 ms for 10^10 integers at 10^12),
-    // and when the range is long enough to amortise the fill launch and the
-    // overflow check's host round trip (at least 2^30 odd integers).
+    // base primes skip most segments, from sqrt(hi) of 2.5 segments of 2^19
+    // bits on (hi of about 1.7e12).  Measured for 10^10 integers, buckets
+    // against the widest segment without them: 1.86 against 1.62 ms at
+    // 10^12 (sqrt(hi) 1.9 segments), 2.12 against 2.32 ms at 3e12 (3.3
+    // segments), 2.72 against 3.72 ms at 10^13.  The range must also be long
+    // enough to amortise the fill launch and the overflow check's host round
+    // trip (at least 2^30 odd integers).
     p.bucket_limit = 0;
     const bool pow2 = (p.seg_bits & (p.seg_bits - 1)) == 0;
     if (t.bucket_limit != 0xffffffffu && pow2 && p.n_segments >= 2) {
         const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
         const bool want = t.bucket_limit ? true
-                                         : 2 * p.sqrt_bound >= 3ull * p.seg_bits && p.nbits >= (1ull << 30);
+                                         : 2 * p.sqrt_bound >= 5ull * p.seg_bits && p.nbits >= (1ull << 30);
         if (want && lim <= p.sqrt_bound && lim < 0xffffffffull)
             p.bucket_limit = static_cast<uint32_t>(lim);
     }
