@@ -67,11 +67,11 @@ typedef struct sieve_ctx sieve_ctx;
  *   seg_bits      odd integers per LDS segment (a multiple of 4096, at most
  *                 622,592 = 19,456 words, the most that two workgroups per
  *                 CU can each hold).  Automatic: a power of two giving about
- *                 two segments per workgroup slot, at most 2^19.  Without hit
- *                 buckets, a range of at least four rounds of 2^19-bit
- *                 segments (8 per CU) takes 622,592, and one of two to four
- *                 rounds takes the smallest multiple of 4096 that still needs
- *                 only that many rounds (every round full).
+ *                 two segments per workgroup slot, at most 2^19.  A range of
+ *                 at least four rounds of 2^19-bit segments (8 per CU) takes
+ *                 622,592, and one of two to four rounds without hit buckets
+ *                 takes the smallest multiple of 4096 that still needs only
+ *                 that many rounds (every round full).
  *   dense_limit   base primes below this are marked by a whole wavefront per
  *                 prime (each lane on four residue classes of the multiples);
  *                 primes at or above it by one lane per prime.  Clamped to
@@ -79,8 +79,8 @@ typedef struct sieve_ctx sieve_ctx;
  *   bucket_limit  base primes at or above this (and at least seg_bits) are
  *                 not scanned per segment: a fill kernel first sorts their
  *                 hits into per-segment buckets in HBM, which the segment
- *                 kernel then applies (plain path; power-of-two seg_bits
- *                 only).  0 = automatic (buckets when sqrt(hi) >= 2.5 *
+ *                 kernel then applies (plain path, any seg_bits).
+ *                 0 = automatic (buckets when sqrt(hi) >= 2.5 *
  *                 seg_bits and the range holds at least 2^30 odd integers),
  *                 0xFFFFFFFF = never.
  *   bucket_depth  entries per segment bucket (0 = from the expected hits

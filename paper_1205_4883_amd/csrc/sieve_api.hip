@@ -110,17 +110,18 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         sw = static_cast<uint32_t>(std::min<uint64_t>(pw, cap));
     }
     if (!t.seg_bits && sw == kDefaultMaxSegWords && max_seg_words(lds_bytes) >= kWideSegWords) {
-        // Long ranges without hit buckets take the widest segment (same
-        // occupancy, less set-up per integer; measured 0.74 -> 0.70 ms on
-        // [2, 1e10)).  Shorter ranges keep 2^19 bits: with under four rounds
-        // of two workgroups per CU a wider segment mostly lengthens the last
-        // round.
+        // Long ranges take the widest segment (same occupancy, less set-up
+        // per integer; measured 0.74 -> 0.70 ms on [2, 1e10), and with hit
+        // buckets 2.72 -> 2.45 ms for 10^10 integers at 10^13, 14.7 -> 13.0
+        // ms at 10^15).  Shorter ranges keep 2^19 bits: with under four
+        // rounds of two workgroups per CU a wider segment mostly lengthens
+        // the last round.
         const uint64_t sb = static_cast<uint64_t>(sw) * 32;
         const bool buckets = t.bucket_limit != 0xffffffffu &&
                              (t.bucket_limit ? true : 2 * p.sqrt_bound >= 5 * sb && p.nbits >= (1ull << 30));
         const uint64_t n_pow2 = (p.n_words + sw - 1) / sw;
         const uint64_t slots = 2ull * n_cu;  // two 1024-thread workgroups per CU
-        if (!buckets && n_pow2 >= 4 * slots) {
+        if (n_pow2 >= 4 * slots) {
             sw = kWideSegWords;
         } else if (!buckets && n_pow2 > slots) {
             // two to four rounds: the same number of rounds, all of them
@@ -140,17 +141,16 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.dense_limit = std::max(p.dense_limit, sv::kFirstMarkedPrime);
     p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
-    // Hit buckets need power-of-two segments and only pay when the largest
-    // base primes skip most segments, from sqrt(hi) of 2.5 segments of 2^19
-    // bits on (hi of about 1.7e12).  Measured for 10^10 integers, buckets
+    // Hit buckets only pay when the largest base primes skip most segments:
+    // from sqrt(hi) of 2.5 segments on (hi of about 2.4e12 with the widest
+    // segment).  Measured for 10^10 integers on 2^19-bit segments, buckets
     // against the widest segment without them: 1.86 against 1.62 ms at
     // 10^12 (sqrt(hi) 1.9 segments), 2.12 against 2.32 ms at 3e12 (3.3
     // segments), 2.72 against 3.72 ms at 10^13.  The range must also be long
     // enough to amortise the fill launch and the overflow check's host round
     // trip (at least 2^30 odd integers).
     p.bucket_limit = 0;
-    const bool pow2 = (p.seg_bits & (p.seg_bits - 1)) == 0;
-    if (t.bucket_limit != 0xffffffffu && pow2 && p.n_segments >= 2) {
+    if (t.bucket_limit != 0xffffffffu && p.n_segments >= 2) {
         const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
         const bool want = t.bucket_limit ? true
                                          : 2 * p.sqrt_bound >= 5ull * p.seg_bits && p.nbits >= (1ull << 30);
@@ -391,9 +391,6 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
 {
     const auto &v = c->h_primes;
     const uint32_t sw = pl.seg_bits / 32;
-    uint32_t seg_log2 = 0;
-    while ((1u << seg_log2) < pl.seg_bits)
-        ++seg_log2;
     // marking primes [0, n_small) are scanned per segment; [n_small, n_mark) are bucketed
     const uint32_t n_below = static_cast<uint32_t>(std::lower_bound(v.begin(), v.end(), pl.bucket_limit) - v.begin());
     const uint32_t n_small = std::min(n_mark, n_below > kPresievePrimes ? n_below - kPresievePrimes : 0u);
@@ -431,7 +428,7 @@ int run_range_bucketed(sieve_ctx *c, const sieve_plan_info &pl, uint64_t lo, uin
             const uint64_t fo = first_odd + 64 * word0;
             HIP_TRY(c, hipMemsetAsync(bcount, 0, segs * sizeof(uint32_t), s));
             HIP_TRY(c, sv::launch_bucket_fill(c->d_primes + kPresievePrimes + n_small,
-                                              c->d_inv + kPresievePrimes + n_small, n_large, fo, seg_log2, segs,
+                                              c->d_inv + kPresievePrimes + n_small, n_large, fo, pl.seg_bits, segs,
                                               buckets, bcount, static_cast<uint32_t>(depth), overflow, s));
             const bool last = w0 + win >= pl.n_segments;
             sv::RangeArgs ra{fo, bits_w, (bits_w + 31) / 32, d_words ? d_words + word0 : nullptr,

@@ -17,8 +17,8 @@ constexpr uint32_t kFirstMarkedPrime = 37;
 // pre-sieve tables, item word and reduction space still fit in a CU's
 // 160 KiB (2 x (792 + 19456) x 4 B plus 136 B each), so a CU keeps 32
 // wavefronts while each segment holds 622,592 odd integers (19% more than
-// 2^19, for less per-segment set-up).  Not a power of two, so hit buckets
-// stay with 2^19-bit segments.
+// 2^19, for less per-segment set-up).  Not a power of two: the bucket fill
+// splits hit offsets by it with a division instead of a shift.
 constexpr uint32_t kWideSegWords = 19456;
 // LDS words taken by the three pre-sieve tables (each is its pattern's
 // period plus one pre-sieve run's words, rounded so the segment starts
@@ -118,13 +118,14 @@ hipError_t launch_range(const RangeArgs &r, const PrimeArgs &p, uint32_t seg_wor
                         hipStream_t s);
 
 // Bucket fill: the hits of primes[0, n_large) (all >= the segment size) on
-// the n_segs segments of 2^seg_log2 bits starting at the odd integer
+// the n_segs segments of seg_bits bits (a multiple of 32, at most 622,592)
+// starting at the odd integer
 // first_odd, in chunks of kBucketChunk segments.  Appends bit offsets to
 // buckets[s * depth ..), counting in bucket_count[s] (zero at launch); sets
 // *overflow when a segment needs more than depth entries.
 constexpr uint32_t kBucketChunk = 32;
 hipError_t launch_bucket_fill(const uint32_t *primes, const double *inv, uint32_t n_large,
-                              uint64_t first_odd, uint32_t seg_log2, uint32_t n_segs, uint32_t *buckets,
+                              uint64_t first_odd, uint32_t seg_bits, uint32_t n_segs, uint32_t *buckets,
                               uint32_t *bucket_count, uint32_t depth, uint32_t *overflow, hipStream_t s);
 
 // inv[i] = 1.0 / primes[i] for i < n.

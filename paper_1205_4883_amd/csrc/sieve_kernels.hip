@@ -964,12 +964,37 @@ __device__ __forceinline__ void walk_hits(uint64_t n0, uint32_t p, double inv, u
     }
 }
 
+// The segment of a chunk that holds bit offset o, and o's offset in it.  A
+// power-of-two segment (seg_log2 > 0) takes shifts.  Otherwise the float
+// quotient o * (1 / seg_bits) is within one of the true one (o < 2^25 and the
+// quotient below 33, so its relative error of a few 2^-24 cannot move it by
+// a whole unit), and one correction step makes it exact.
+__device__ __forceinline__ uint32_t seg_split(uint32_t o, uint32_t seg_bits, uint32_t seg_log2, float rcp,
+                                              uint32_t &off)
+{
+    if (seg_log2) {
+        off = o & (seg_bits - 1u);
+        return o >> seg_log2;
+    }
+    uint32_t q = static_cast<uint32_t>(static_cast<float>(o) * rcp);
+    uint32_t b = __umul24(q, seg_bits);  // q < 33, seg_bits < 2^24
+    if (b > o) {
+        --q;
+        b -= seg_bits;
+    } else if (o - b >= seg_bits) {
+        ++q;
+        b += seg_bits;
+    }
+    off = o - b;
+    return q;
+}
+
 // One workgroup: a chunk of kBucketChunk segments (blockIdx.y) against 256
 // large primes (blockIdx.x).  Two passes over the same hits: the first
 // counts them per segment in LDS, then one global atomic per segment
 // reserves room in its bucket, and the second writes each hit at its rank.
 __global__ void __launch_bounds__(256) bucket_fill_kernel(const uint32_t *primes, const double *inv,
-                                                          uint32_t n_large, uint64_t first_odd, uint32_t seg_log2,
+                                                          uint32_t n_large, uint64_t first_odd, uint32_t seg_bits,
                                                           uint32_t n_segs, uint32_t *buckets, uint32_t *bucket_count,
                                                           uint32_t depth, uint32_t *overflow)
 {
@@ -979,8 +1004,10 @@ __global__ void __launch_bounds__(256) bucket_fill_kernel(const uint32_t *primes
     const uint32_t i = blockIdx.x * blockDim.x + t;
     const uint32_t seg0 = blockIdx.y * kBucketChunk;
     const uint32_t segs = min(kBucketChunk, n_segs - seg0);
-    const uint32_t chunk_bits = segs << seg_log2;
-    const uint64_t n0 = first_odd + (static_cast<uint64_t>(seg0) << (seg_log2 + 1));
+    const uint32_t chunk_bits = segs * seg_bits;  // at most 32 x 622,592 < 2^25
+    const uint64_t n0 = first_odd + 2 * static_cast<uint64_t>(seg0) * seg_bits;
+    const uint32_t seg_log2 = (seg_bits & (seg_bits - 1u)) == 0 ? 31u - __builtin_clz(seg_bits) : 0u;
+    const float rcp = 1.0f / static_cast<float>(seg_bits);
     if (t < kBucketChunk)
         cnt[t] = 0;
     __syncthreads();
@@ -988,7 +1015,10 @@ __global__ void __launch_bounds__(256) bucket_fill_kernel(const uint32_t *primes
     const uint32_t p = live ? primes[i] : 0;
     const double pinv = live ? inv[i] : 0.0;
     if (live)
-        walk_hits(n0, p, pinv, chunk_bits, [&](uint32_t o) { atomicAdd(&cnt[o >> seg_log2], 1u); });
+        walk_hits(n0, p, pinv, chunk_bits, [&](uint32_t o) {
+            uint32_t off;
+            atomicAdd(&cnt[seg_split(o, seg_bits, seg_log2, rcp, off)], 1u);
+        });
     __syncthreads();
     if (t < segs) {
         base[t] = atomicAdd(&bucket_count[seg0 + t], cnt[t]);
@@ -996,12 +1026,12 @@ __global__ void __launch_bounds__(256) bucket_fill_kernel(const uint32_t *primes
     }
     __syncthreads();
     if (live) {
-        const uint32_t mask = (1u << seg_log2) - 1u;
         walk_hits(n0, p, pinv, chunk_bits, [&](uint32_t o) {
-            const uint32_t s = o >> seg_log2;
+            uint32_t off;
+            const uint32_t s = seg_split(o, seg_bits, seg_log2, rcp, off);
             const uint32_t slot = base[s] + atomicAdd(&cnt[s], 1u);
             if (slot < depth)
-                buckets[static_cast<uint64_t>(seg0 + s) * depth + slot] = o & mask;
+                buckets[static_cast<uint64_t>(seg0 + s) * depth + slot] = off;
             else
                 atomicOr(overflow, 1u);
         });
@@ -1050,13 +1080,13 @@ hipError_t launch_bootstrap_primes(uint32_t *d_out, uint32_t *d_count, hipStream
 }
 
 hipError_t launch_bucket_fill(const uint32_t *primes, const double *inv, uint32_t n_large,
-                              uint64_t first_odd, uint32_t seg_log2, uint32_t n_segs, uint32_t *buckets,
+                              uint64_t first_odd, uint32_t seg_bits, uint32_t n_segs, uint32_t *buckets,
                               uint32_t *bucket_count, uint32_t depth, uint32_t *overflow, hipStream_t s)
 {
     if (n_large == 0 || n_segs == 0)
         return hipSuccess;
     const dim3 grid((n_large + 255) / 256, (n_segs + kBucketChunk - 1) / kBucketChunk);
-    hipLaunchKernelGGL(bucket_fill_kernel, grid, dim3(256), 0, s, primes, inv, n_large, first_odd, seg_log2,
+    hipLaunchKernelGGL(bucket_fill_kernel, grid, dim3(256), 0, s, primes, inv, n_large, first_odd, seg_bits,
                        n_segs, buckets, bucket_count, depth, overflow);
     return hipGetLastError();
 }

@@ -99,22 +99,29 @@ def test_plan_tuning_resolution():
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 13))
     assert p["block_threads"] == 256 and p["dense_limit"] == 128
     assert sv.sieve_plan(2, 10**7)["dense_limit"] == 128
-    # hit buckets: automatic once sqrt(hi) reaches 2.5 segments of 2^19 bits
-    # (2 sqrt >= 5 x 524288, hi >= about 1.718e12) on a range of at least
-    # 2^30 odd integers
-    assert sv.sieve_plan(3 * 10**12, 3 * 10**12 + 10**10)["bucket_limit"] == 1 << 19
-    assert sv.sieve_plan(3 * 10**12, 3 * 10**12 + 10**10)["seg_bits"] == 1 << 19  # buckets keep 2^19
-    for lo in (10**11, 10**12):
+    # hit buckets: automatic once sqrt(hi) reaches 2.5 segments (2 sqrt >= 5 x
+    # 622592 for the widest segment, which long ranges take: hi >= about
+    # 2.42e12) on a range of at least 2^30 odd integers
+    p = sv.sieve_plan(3 * 10**12, 3 * 10**12 + 10**10)
+    assert p["bucket_limit"] == 622592 and p["seg_bits"] == 622592
+    for lo in (10**11, 10**12, 2 * 10**12):
         p = sv.sieve_plan(lo, lo + 10**10)
         assert p["bucket_limit"] == 0 and p["seg_bits"] == 622592
-    edge = 1310720 ** 2  # sqrt(hi) = 2.5 segments exactly
+    edge = 1556480 ** 2  # sqrt(hi) = 2.5 widest segments exactly
     assert sv.sieve_plan(edge - 2**32, edge)["bucket_limit"] == 0
-    assert sv.sieve_plan(edge - 2**32, edge + 2**22)["bucket_limit"] == 1 << 19
+    assert sv.sieve_plan(edge - 2**32, edge + 2**22)["bucket_limit"] == 622592
+    # 2^30 odd integers (the least that buckets take) are four rounds of
+    # 2^19-bit segments on 256 CUs, so a bucketed range always has the widest
+    # segment
+    p = sv.sieve_plan(3 * 10**12, 3 * 10**12 + 2**31)
+    assert p["seg_bits"] == 622592 and p["bucket_limit"] == 622592
     assert sv.sieve_plan(3 * 10**12, 3 * 10**12 + 2**31 - 2)["bucket_limit"] == 0
-    assert sv.sieve_plan(3 * 10**12, 3 * 10**12 + 2**31)["bucket_limit"] == 1 << 19
     assert sv.sieve_plan(10**11, 10**11 + 10**6)["bucket_limit"] == 0
     p = sv.sieve_plan(3 * 10**12, 3 * 10**12 + 10**10, tuning=dict(bucket_limit=0xFFFFFFFF))
     assert p["bucket_limit"] == 0 and p["seg_bits"] == 622592
+    # any segment size can take buckets (the fill divides by it)
+    p = sv.sieve_plan(10**13, 10**13 + 10**9, tuning=dict(seg_bits=491520, bucket_limit=491520))
+    assert p["bucket_limit"] == 491520 and p["seg_bits"] == 491520
     # the widest segment can be asked for; anything wider cannot
     assert sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=622592))["seg_bits"] == 622592
 

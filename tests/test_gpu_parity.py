@@ -470,6 +470,10 @@ def test_autotune_bucketed_range(gpu, oracle_mod, sv_mod):
     (10**12, 10**12 + 2 * 10**7, 65536, 65536, 64),      # tiny depth: overflow, retry
     (10**13 - 3, 10**13 + 2 * 10**7, 131072, 0, 0),      # automatic choice
     (10**15 - 2**31, 10**15, 0, 0, 0),                   # automatic at the top of the domain
+    # segments that are not a power of two: the fill divides offsets by them
+    (10**12 + 7, 10**12 + 6 * 10**7 + 3, 622592, 622592, 0),
+    (10**13 + 1, 10**13 + 3 * 10**7, 491520, 491520, 0),
+    (10**12, 10**12 + 2 * 10**7, 622592, 622592, 64),    # tiny depth: overflow, retry
 ])
 def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth):
     gpu.tuning(seg_bits=seg_bits, bucket_limit=limit, bucket_depth=depth)
