@@ -80,7 +80,7 @@ typedef struct sieve_ctx sieve_ctx;
  *                 not scanned per segment: a fill kernel first sorts their
  *                 hits into per-segment buckets in HBM, which the segment
  *                 kernel then applies (plain path, any seg_bits).
- *                 0 = automatic (buckets when sqrt(hi) >= 2.5 *
+ *                 0 = automatic (buckets when sqrt(hi) >= 2 *
  *                 seg_bits and the range holds at least 2^30 odd integers),
  *                 0xFFFFFFFF = never.
  *   bucket_depth  entries per segment bucket (0 = from the expected hits

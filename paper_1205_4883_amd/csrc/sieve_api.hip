@@ -118,7 +118,7 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
         // the last round.
         const uint64_t sb = static_cast<uint64_t>(sw) * 32;
         const bool buckets = t.bucket_limit != 0xffffffffu &&
-                             (t.bucket_limit ? true : 2 * p.sqrt_bound >= 5 * sb && p.nbits >= (1ull << 30));
+                             (t.bucket_limit ? true : p.sqrt_bound >= 2 * sb && p.nbits >= (1ull << 30));
         const uint64_t n_pow2 = (p.n_words + sw - 1) / sw;
         const uint64_t slots = 2ull * n_cu;  // two 1024-thread workgroups per CU
         if (n_pow2 >= 4 * slots) {
@@ -142,18 +142,18 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
     p.block_threads = t.block_threads ? t.block_threads : default_threads(sw);
     p.n_segments = (p.n_words + sw - 1) / sw;
     // Hit buckets only pay when the largest base primes skip most segments:
-    // from sqrt(hi) of 2.5 segments on (hi of about 2.4e12 with the widest
-    // segment).  Measured for 10^10 integers on 2^19-bit segments, buckets
-    // against the widest segment without them: 1.86 against 1.62 ms at
-    // 10^12 (sqrt(hi) 1.9 segments), 2.12 against 2.32 ms at 3e12 (3.3
-    // segments), 2.72 against 3.72 ms at 10^13.  The range must also be long
-    // enough to amortise the fill launch and the overflow check's host round
-    // trip (at least 2^30 odd integers).
+    // from sqrt(hi) of two segments on (hi of about 1.55e12 with the widest
+    // segment).  Measured for 10^10 integers on the widest segment, buckets
+    // against none: 1.80 against 1.88 ms at 1.6e12 (sqrt(hi) 2.03
+    // segments), 1.93 against 2.02 ms at 2e12, 2.46 against 3.72 ms at
+    // 10^13; below two segments the gain comes and goes (1.64 against 1.62
+    // ms at 10^12, 1.65 against 1.72 ms at 1.2e12).  The range must also be
+    // long enough to amortise the fill launch and the overflow check's host
+    // round trip (at least 2^30 odd integers).
     p.bucket_limit = 0;
     if (t.bucket_limit != 0xffffffffu && p.n_segments >= 2) {
         const uint64_t lim = std::max<uint64_t>(t.bucket_limit ? t.bucket_limit : p.seg_bits, p.seg_bits);
-        const bool want = t.bucket_limit ? true
-                                         : 2 * p.sqrt_bound >= 5ull * p.seg_bits && p.nbits >= (1ull << 30);
+        const bool want = t.bucket_limit ? true : p.sqrt_bound >= 2ull * p.seg_bits && p.nbits >= (1ull << 30);
         if (want && lim <= p.sqrt_bound && lim < 0xffffffffull)
             p.bucket_limit = static_cast<uint32_t>(lim);
     }

@@ -99,15 +99,16 @@ def test_plan_tuning_resolution():
     p = sv.sieve_plan(2, 10**10, tuning=dict(seg_bits=1 << 13))
     assert p["block_threads"] == 256 and p["dense_limit"] == 128
     assert sv.sieve_plan(2, 10**7)["dense_limit"] == 128
-    # hit buckets: automatic once sqrt(hi) reaches 2.5 segments (2 sqrt >= 5 x
-    # 622592 for the widest segment, which long ranges take: hi >= about
-    # 2.42e12) on a range of at least 2^30 odd integers
-    p = sv.sieve_plan(3 * 10**12, 3 * 10**12 + 10**10)
-    assert p["bucket_limit"] == 622592 and p["seg_bits"] == 622592
-    for lo in (10**11, 10**12, 2 * 10**12):
+    # hit buckets: automatic once sqrt(hi) reaches two segments (622592 bits
+    # for the widest segment, which long ranges take: hi >= about 1.55e12) on
+    # a range of at least 2^30 odd integers
+    for lo in (2 * 10**12, 3 * 10**12):
+        p = sv.sieve_plan(lo, lo + 10**10)
+        assert p["bucket_limit"] == 622592 and p["seg_bits"] == 622592
+    for lo in (10**11, 10**12):
         p = sv.sieve_plan(lo, lo + 10**10)
         assert p["bucket_limit"] == 0 and p["seg_bits"] == 622592
-    edge = 1556480 ** 2  # sqrt(hi) = 2.5 widest segments exactly
+    edge = 1245184 ** 2  # sqrt(hi) = two widest segments exactly
     assert sv.sieve_plan(edge - 2**32, edge)["bucket_limit"] == 0
     assert sv.sieve_plan(edge - 2**32, edge + 2**22)["bucket_limit"] == 622592
     # 2^30 odd integers (the least that buckets take) are four rounds of
