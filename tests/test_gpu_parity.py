@@ -474,6 +474,8 @@ def test_autotune_bucketed_range(gpu, oracle_mod, sv_mod):
     (10**12 + 7, 10**12 + 6 * 10**7 + 3, 622592, 622592, 0),
     (10**13 + 1, 10**13 + 3 * 10**7, 491520, 491520, 0),
     (10**12, 10**12 + 2 * 10**7, 622592, 622592, 64),    # tiny depth: overflow, retry
+    # automatic, just past the threshold (sqrt(hi) of two widest segments)
+    (1_600_000_000_001, 1_600_000_000_001 + 2**31, 0, 0, 0),
 ])
 def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth):
     gpu.tuning(seg_bits=seg_bits, bucket_limit=limit, bucket_depth=depth)
@@ -481,6 +483,8 @@ def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth
         plan = sv_mod.sieve_plan(lo, hi, tuning=gpu.tuning())
         if limit or hi >= 10**15:
             assert plan["bucket_limit"] > 0
+        if not seg_bits and lo == 1_600_000_000_001:
+            assert plan["bucket_limit"] == plan["seg_bits"] == 622592
         _cmp_bitmap(gpu, oracle_mod, lo, hi)
     finally:
         gpu.tuning(seg_bits=0, bucket_limit=0, bucket_depth=0)
