@@ -244,15 +244,15 @@ SIEVE_API int sieve_is_prime_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t
 SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t count, const uint64_t *d_draws,
                                  uint32_t iterations, uint8_t *d_out, void *stream);
 
-/* Autotuner.  Times candidate tunings (the automatic plan, then segment
- * sizes with a matching workgroup size times three dense/sparse bounds) on
- * the given work, so the answer is never slower than the untuned context,
- * then refines the winner: one or two resident workgroups per CU and, for a
- * single range that uses hit buckets, a large-prime threshold of 2x or 4x
- * the segment size or no buckets - one
- * interval is timed as sieve_range_count, several as a count-only
- * sieve_batch - and returns the fastest in *best (and its kernel time in
- * *best_ms if not NULL).  Results are cached per context by (single range
+/* Autotuner.  Times candidate tunings on the given work and returns the
+ * fastest in *best (and its kernel time in *best_ms if not NULL).  The
+ * candidates are the automatic plan first (so the answer is never slower
+ * than the untuned context), then four segment sizes, each with a matching
+ * workgroup size and three dense/sparse bounds.  The winner is then refined:
+ * one or two resident workgroups per CU, and, for a single range that uses
+ * hit buckets, a large-prime threshold of 2x or 4x the segment size, or no
+ * buckets.  One interval is timed as sieve_range_count, several as a
+ * count-only sieve_batch.  Results are cached per context by (single range
  * or batch, decade of the largest hi, log2 of the total bitmap words); a
  * cached answer is returned without timing unless SIEVE_TUNE_FORCE is set.
  * With SIEVE_TUNE_APPLY the context keeps the winner; otherwise its tuning
