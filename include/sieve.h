@@ -197,6 +197,35 @@ SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64
 SIEVE_API int sieve_range_bitmap(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t *d_words,
                        uint64_t n_words, uint64_t *pi_out, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * sieve as sieve_range_bitmap (and, with d_words == NULL, as
+ * sieve_range_count), computing exactly the same words and count, but the
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and never waits on the host:
+ *   - the launch's work queues and partial counts live in a 4,352-byte
+ *     device array inside the library, one per GPU, held until the process
+ *     ends (its address is looked up by sieve_create);
+ *   - the base primes must already be resident in ctx: isqrt(hi - 1) must
+ *     not exceed the context's table (2^20 after sieve_create, i.e. any
+ *     hi <= 1,099,513,724,929; grow it beforehand with sieve_base_primes);
+ *   - no hit buckets are used (their pool is allocated on demand), so
+ *     ranges above about 1.5e12 run slower than through sieve_range_bitmap,
+ *     with the same result.
+ * d_words: DEVICE buffer of n_words >= sieve_bitmap_words(lo, hi) words, or
+ *   NULL to count only.  d_pi: DEVICE word (8-byte aligned) that receives
+ *   pi over [lo, hi) (the even prime 2 included), or NULL.  Both are written
+ *   in stream order on `stream` (NULL = default stream); the call returns
+ *   once the work is queued.
+ * Every call on one GPU shares that GPU's counter array: calls that overlap
+ * on one GPU (from several host threads, or on several streams without an
+ * order between them) race and give wrong counts.  Order them on one stream.
+ * Errors: SIEVE_EINVAL (ctx NULL, lo > hi, misaligned pointers),
+ * SIEVE_ERANGE (hi > SIEVE_MAX_HI, or base primes beyond the resident
+ * table), SIEVE_EBUFSZ (n_words too small), SIEVE_ENODEV, SIEVE_EDEVICE. */
+SIEVE_API int sieve_range_bitmap_noalloc(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint32_t *d_words,
+                                         uint64_t n_words, unsigned long long *d_pi, void *stream);
+
 /* One interval of a batch.  flags bit 0: write its bitmap at
  * d_words[word_offset ..); the range's words must lie inside total_words. */
 typedef struct sieve_interval {

@@ -8,7 +8,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsieve.so")
-SOURCES = ["sieve_kernels.hip", "sieve_api.hip", "sieve_serve.hip", "sieve_primality.hip"]
+SOURCES = ["sieve_kernels.hip", "sieve_api.hip", "sieve_serve.hip", "sieve_primality.hip",
+           "sieve_noalloc.hip"]
 
 
 def hipcc_command(out):

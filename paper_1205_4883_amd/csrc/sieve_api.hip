@@ -964,6 +964,8 @@ int sieve_create(sieve_ctx **out, int hip_device, uint64_t hbm_budget_bytes)
     if (st == SIEVE_OK)
         st = sv::engine_init(c, c->batch);
     if (st == SIEVE_OK)
+        st = sv::noalloc_setup(c);
+    if (st == SIEVE_OK)
         st = sv::ensure_primes(c, sv::kDefaultPrimeLimit);
     if (st != SIEVE_OK) {
         sieve_destroy(c);

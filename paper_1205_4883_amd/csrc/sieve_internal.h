@@ -58,13 +58,14 @@ struct RangeArgs {
     uint32_t *counters;  // kCounterWords words, all zero at launch
     bool count;          // count the 1 bits (primes)
     bool last;           // the call's last launch: publish the count and clear it
-    unsigned long long *publish;  // where the last launch stores the count (host-mapped), or null
+    unsigned long long *publish;  // where the last launch stores the count (host-mapped or device), or null
     // Large-prime hit buckets of this launch's segments, or null: segment s
     // owns buckets[s * bucket_depth ..) with min(bucket_count[s], depth)
     // entries, each a bit offset inside the segment.
     const uint32_t *buckets;
     const uint32_t *bucket_count;
     uint32_t bucket_depth;
+    uint32_t publish_add;  // added to the published count (the even prime 2, when in range)
 };
 
 // The marking primes of one launch: odd primes >= 37, ascending.

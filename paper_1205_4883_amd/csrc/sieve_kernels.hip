@@ -600,7 +600,7 @@ __device__ void finish_launch(const RangeArgs &r, unsigned long long wg_count)
     }
     __hip_atomic_store(all, r.last ? 0ull : total << 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (r.last && r.publish)
-        *r.publish = total;  // the host reads it after synchronising with the stream
+        *r.publish = total + r.publish_add;  // read after the stream (or the published word) says so
 }
 
 // Sieve segment `seg` of one range into LDS and emit its words; returns the

@@ -134,6 +134,12 @@ uint64_t isqrt_u64(uint64_t n);
 int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, uint32_t lds_bytes,
               sieve_plan_info *out);
 int ensure_primes(sieve_ctx *c, uint64_t bound);
+// Workgroups of the plain range kernel resident on the whole device for a plan.
+uint32_t resident_blocks(const sieve_ctx *c, const sieve_plan_info &pl, bool write);
+// Once per device, with the context's device current: find the device
+// address of the allocation-free call's counter array and clear it
+// (sieve_noalloc.hip).
+int noalloc_setup(sieve_ctx *c);
 void marking_primes(const sieve_ctx *c, uint64_t r, uint32_t dense_limit, uint32_t *n_mark,
                     uint32_t *n_dense);
 // The plain path: sieve [lo, hi) into d_words (may be null) and/or count it.

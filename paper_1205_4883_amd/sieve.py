@@ -29,6 +29,7 @@ EXPORTED = [
     "sieve_set_timing", "sieve_last_kernel_ms",
     "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
     "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
+    "sieve_range_bitmap_noalloc",
     "sieve_autotune", "sieve_is_prime_batch", "sieve_fermat_batch",
     "sieve_server_create", "sieve_server_submit", "sieve_server_poll", "sieve_server_release",
     "sieve_server_get_stats", "sieve_server_destroy", "sieve_serve_trace",
@@ -121,6 +122,7 @@ def _lib():
     lib.sieve_range_count.argtypes = [vp, u64, u64, u64p, vp]
     lib.sieve_range_bitmap.argtypes = [vp, u64, u64, vp, u64, u64p, vp]
     lib.sieve_batch.argtypes = [vp, vp, u32, vp, u64, vp, vp]
+    lib.sieve_range_bitmap_noalloc.argtypes = [vp, u64, u64, vp, u64, vp, vp]
     lib.sieve_is_prime_batch.argtypes = [vp, vp, u64, vp, vp]
     lib.sieve_fermat_batch.argtypes = [vp, vp, u64, vp, u32, vp, vp]
     lib.sieve_autotune.argtypes = [vp, vp, u32, u32, ctypes.POINTER(sieve_tuning),
@@ -228,6 +230,15 @@ def sieve_range_bitmap(ctx, lo, hi, d_words, n_words, want_pi=True, stream=None)
                                      ctypes.byref(pi) if want_pi else None, _stream_ptr(stream)),
            "sieve_range_bitmap")
     return pi.value if want_pi else None
+
+
+def sieve_range_bitmap_noalloc(ctx, lo, hi, d_words, n_words, d_pi, stream=None):
+    """The allocation-free call: d_words (bitmap, or None to count only) and
+    d_pi (one int64 element receiving pi, or None) are device tensors or
+    addresses, written in stream order; nothing is allocated or waited on."""
+    _check(_lib().sieve_range_bitmap_noalloc(ctx, lo, hi, ctypes.c_void_p(_ptr(d_words)), n_words,
+                                             ctypes.c_void_p(_ptr(d_pi)), _stream_ptr(stream)),
+           "sieve_range_bitmap_noalloc")
 
 
 def sieve_batch(ctx, intervals, d_words=None, total_words=0, stream=None):
