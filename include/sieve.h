@@ -162,10 +162,14 @@ SIEVE_API int sieve_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tuning, u
  * ceil((hi/2 - lo/2) / 32).  Pure; 0 when lo >= hi. */
 SIEVE_API uint64_t sieve_bitmap_words(uint64_t lo, uint64_t hi);
 
-/* The base primes (step A1): all primes p <= limit in ascending order,
- * including 2, copied into the HOST buffer out[0 .. cap).  The table is
- * computed on the device (a one-workgroup bootstrap sieve below 2^16, then the
- * range sieve and a compaction kernel) and kept resident in the context.
+/* The base primes: all primes p <= limit in ascending order, including 2.
+ * The paper's sieve crosses off the multiples of every prime up to the
+ * square root of the limit (Section 1, where trial division also stops at
+ * sqrt(n); Section 3.1), so a range [lo, hi) needs the primes up to
+ * isqrt(hi - 1).  They are copied into the HOST buffer out[0 .. cap).  The
+ * table is computed on the device (a one-workgroup bootstrap sieve below
+ * 2^16, then the range sieve and a compaction kernel) and kept resident in
+ * the context.
  * limit <= isqrt(SIEVE_MAX_HI) + 1.  out == NULL or cap == 0 is a size query:
  * only *n_out is written.  Errors: SIEVE_EINVAL (ctx or n_out NULL),
  * SIEVE_ERANGE (limit too large), SIEVE_EBUFSZ (cap < count; *n_out = count),
@@ -173,17 +177,23 @@ SIEVE_API uint64_t sieve_bitmap_words(uint64_t lo, uint64_t hi);
 SIEVE_API int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint32_t *out, uint64_t cap,
                       uint64_t *n_out);
 
-/* pi over [lo, hi) (steps A1-A6, A8): the number of primes p with
- * lo <= p < hi.  No bitmap is written.  Blocks until *pi_out is valid: it
- * returns as soon as the launch's last workgroup has published the count to
- * pinned host memory, without synchronising `stream` (later work on the
+/* pi over [lo, hi): the number of primes p with lo <= p < hi, i.e.
+ * pi(hi - 1) - pi(lo - 1) for the prime-counting function pi(x) of Section 1.
+ * The range is sieved as the paper's Section 3.1 describes (the multiples of
+ * each base prime crossed off, the n integers cut into ceil(n/k) blocks
+ * that are sieved independently, Eq. 3), each block an LDS segment.  No
+ * bitmap is written.  Blocks until *pi_out is valid: it returns as soon as
+ * the launch's last workgroup has published the count to pinned host
+ * memory, without synchronising `stream` (later work on the
  * stream stays ordered after the launch).
  * Errors: SIEVE_EINVAL (ctx or pi_out NULL, lo > hi), SIEVE_ERANGE,
  * SIEVE_ENOMEM, SIEVE_EDEVICE. */
 SIEVE_API int sieve_range_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *pi_out,
                       void *stream);
 
-/* The odd-only prime bitmap of [lo, hi) (steps A1-A8) written to the DEVICE
+/* The primes of [lo, hi) themselves (the sieve of Section 1 lists every
+ * prime up to its limit), sieved block by block as in Section 3.1 (Eq. 3),
+ * as an odd-only bitmap written to the DEVICE
  * buffer d_words[0 .. n_words); words past sieve_bitmap_words(lo, hi) are not
  * touched.  d_words must be 4-byte aligned.  The words are written in
  * stream order: later work on `stream` (a copy, a kernel, torch operations on
