@@ -306,12 +306,14 @@ SIEVE_API int sieve_autotune(sieve_ctx *ctx, const sieve_interval *iv, uint32_t 
  * Serving: a request loop with continuous batching.
  *
  * A server owns its own context on one device and a dispatcher thread.
- * Requests (ranges) are admitted in arrival order while the device bytes
- * they hold (their bitmaps) fit the HBM budget and their returned bitmaps fit
- * the pinned host arena; admitted requests are packed into batches (the
- * sieve_batch work queue) on up to `lanes` streams at once, so requests that
- * arrive while others run are batched and overlap on the device.  Results
- * are identical to sieving each range alone.
+ * Requests (ranges) are admitted in arrival order while their bitmaps get
+ * room in two budgets that are real memory: a device pool of the HBM budget
+ * (less the server's fixed device memory, allocated once at creation) and a
+ * pinned host arena for the returned bitmaps.  Admitted requests are packed
+ * into batches (the sieve_batch work queue) on up to `lanes` streams at
+ * once, so requests that arrive while others run are batched and overlap on
+ * the device (the paper's overlap of communication and computation,
+ * Section 2.2).  Results are identical to sieving each range alone.
  * ---------------------------------------------------------------------- */
 typedef struct sieve_server sieve_server;
 
@@ -322,10 +324,15 @@ typedef struct sieve_server sieve_server;
 typedef struct sieve_server_config {
     uint32_t lanes;            /* batches in flight at once, one stream each [3] */
     uint32_t max_batch;        /* requests per batch [1024] */
-    uint64_t max_batch_words;  /* bitmap words per batch: each lane's device
-                                  output buffer [2^26 = 256 MiB] */
-    uint64_t hbm_budget_bytes; /* device bytes admitted requests may hold [32 GiB] */
-    uint64_t host_arena_bytes; /* pinned host memory for returned bitmaps [2 GiB] */
+    uint64_t max_batch_words;  /* bitmap words per batch, and the largest
+                                  bitmap one request may ask for [2^26] */
+    uint64_t hbm_budget_bytes; /* device bytes the server holds [32 GiB]: 64 MiB
+                                  for its context (the full base-prime table),
+                                  each lane's batch buffers (plain mode: the
+                                  256 MiB hit-bucket pool), and the rest as the
+                                  pool the admitted bitmaps live in */
+    uint64_t host_arena_bytes; /* pinned host memory for returned bitmaps,
+                                  held until released [2 GiB] */
     uint32_t mode;             /* SIEVE_SERVE_BATCHED or SIEVE_SERVE_PLAIN */
     uint32_t pad;
 } sieve_server_config;
@@ -356,17 +363,25 @@ typedef struct sieve_server_stats {
     uint64_t max_batch_seen;    /* most requests in one batch */
     uint64_t max_inflight;      /* most batches on the device at once */
     uint64_t deferred;          /* admissions that had to wait for budget */
-    uint64_t peak_admitted_bytes;
+    uint64_t peak_admitted_bytes; /* most device pool bytes held by admitted requests */
+    uint64_t peak_host_bytes;   /* most pinned arena bytes held (until release) */
+    uint64_t device_pool_bytes; /* size of the device bitmap pool */
+    uint64_t graph_captures;    /* batch graphs captured after creation (0 unless a
+                                   batch outgrew the buffers sized at creation) */
 } sieve_server_stats;
 
-/* Start a server on HIP device hip_device (cfg NULL = defaults).  Errors:
- * SIEVE_EINVAL, SIEVE_ENODEV, SIEVE_ENOMEM, SIEVE_EDEVICE. */
+/* Start a server on HIP device hip_device (cfg NULL = defaults).  Builds the
+ * full base-prime table, allocates the device pool and the host arena and
+ * captures each lane's batch graphs before returning.  Errors:
+ * SIEVE_EINVAL, SIEVE_ENODEV, SIEVE_ENOMEM (also: the HBM budget does not
+ * cover the fixed device memory), SIEVE_EDEVICE. */
 SIEVE_API int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_server **out);
 
 /* Queue the range [lo, hi); flags: SIEVE_WANT_BITMAP to get its bitmap back.
  * Returns at once with the request id.  Errors: SIEVE_EINVAL (lo > hi, NULL
- * id_out), SIEVE_ERANGE (hi > SIEVE_MAX_HI), SIEVE_ENOMEM (the request alone
- * exceeds a budget or the lane buffer). */
+ * id_out), SIEVE_ERANGE (hi > SIEVE_MAX_HI), SIEVE_ENOMEM (its bitmap alone
+ * exceeds max_batch_words or the largest block of the device pool or host
+ * arena). */
 SIEVE_API int sieve_server_submit(sieve_server *s, uint64_t lo, uint64_t hi, uint32_t flags,
                                   uint64_t *id_out);
 
@@ -388,8 +403,9 @@ SIEVE_API int sieve_server_destroy(sieve_server *s);
 /* Replay a timed trace through a server: request i (lo[i], hi[i],
  * flags[i]) is submitted at t_arrival_s[i] seconds after the start by a
  * native submitter thread; results are released as they arrive.  Fills
- * pi_out[i] and latency_ms_out[i] (arrival to result on the host), and
- * stats_out if not NULL. */
+ * pi_out[i] and latency_ms_out[i] (from the scheduled arrival, start +
+ * t_arrival_s[i], to the result on the host, so a submitter running late
+ * counts as queueing), and stats_out if not NULL. */
 SIEVE_API int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint64_t *lo,
                                 const uint64_t *hi, const uint32_t *flags, const double *t_arrival_s,
                                 uint64_t n, uint64_t *pi_out, double *latency_ms_out,

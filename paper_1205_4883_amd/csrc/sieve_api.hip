@@ -631,21 +631,23 @@ int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes)
 
 namespace {
 
-void drop_graph(BatchEngine &e)
+void drop_graph(BatchEngine &e, int v)
 {
-    if (e.exec)
-        (void)hipGraphExecDestroy(e.exec);
-    if (e.graph)
-        (void)hipGraphDestroy(e.graph);
-    e.exec = nullptr;
-    e.graph = nullptr;
+    if (e.exec[v])
+        (void)hipGraphExecDestroy(e.exec[v]);
+    if (e.graph[v])
+        (void)hipGraphDestroy(e.graph[v]);
+    e.exec[v] = nullptr;
+    e.graph[v] = nullptr;
 }
 
 // Capture the batch launch sequence on the context's own stream (capture runs
-// nothing) and instantiate it; the graph may then be launched on any stream.
+// nothing) and instantiate it into the engine's slot for k.small; the graph
+// may then be launched on any stream.
 int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
 {
-    drop_graph(eng);
+    const int v = k.small ? 1 : 0;
+    drop_graph(eng, v);
     hipStream_t cs = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = sv::launch_batch(static_cast<sv::BatchHeader *>(const_cast<void *>(k.blob)),
@@ -662,16 +664,17 @@ int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
     if (e == hipSuccess)
         e = e2;
     if (e == hipSuccess)
-        e = hipGraphInstantiate(&eng.exec, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&eng.exec[v], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         if (g)
             (void)hipGraphDestroy(g);
-        eng.exec = nullptr;
+        eng.exec[v] = nullptr;
         c->last_hip = e;
         return SIEVE_EDEVICE;
     }
-    eng.graph = g;
-    eng.key = k;
+    eng.graph[v] = g;
+    eng.key[v] = k;
+    ++eng.captures;
     return SIEVE_OK;
 }
 
@@ -714,7 +717,8 @@ void engine_free(BatchEngine &e)
 {
     if (e.done && e.pending)
         (void)hipEventSynchronize(e.done);
-    drop_graph(e);
+    drop_graph(e, 0);
+    drop_graph(e, 1);
     for (DevBuf *b : {&e.blob, &e.counts, &e.item_counts})
         if (b->p)
             (void)hipFree(b->p);
@@ -726,15 +730,26 @@ void engine_free(BatchEngine &e)
     e = BatchEngine();
 }
 
+uint32_t batch_seg_words(const sieve_ctx *c)
+{
+    // a batch never uses hit buckets, so it takes the widest segment two
+    // workgroups per CU can hold (measured 3.52 -> 3.3 ms on 4096 intervals)
+    const uint32_t cap = std::min(max_seg_words(c->lds_max), kWideSegWords);
+    return c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
+}
+
+uint64_t engine_device_bytes(uint32_t n, uint64_t items)
+{
+    return blob_bytes(n, items) + std::max<uint64_t>(1, n) * sizeof(unsigned long long) +
+           std::max<uint64_t>(1, items) * sizeof(uint32_t);
+}
+
 int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                  uint64_t total_words)
 {
     if (int st = validate_tuning(c->tuning, c->lds_max))
         return st;
-    // a batch never uses hit buckets, so it takes the widest segment two
-    // workgroups per CU can hold (measured 3.52 -> 3.3 ms on 4096 intervals)
-    const uint32_t cap = std::min(max_seg_words(c->lds_max), kWideSegWords);
-    const uint32_t sw = c->tuning.seg_bits ? c->tuning.seg_bits / 32 : cap;
+    const uint32_t sw = batch_seg_words(c);
     const uint32_t dense_limit = std::max(c->tuning.dense_limit ? c->tuning.dense_limit : default_dense_limit(sw * 32),
                                           sv::kFirstMarkedPrime);
     const uint32_t threads = c->tuning.block_threads ? c->tuning.block_threads : default_threads(sw);
@@ -842,11 +857,8 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     return SIEVE_OK;
 }
 
-int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed)
+int engine_graph(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, bool small)
 {
-    const uint32_t n = e.n;
-    if (int st = engine_reserve(c, e, n, e.items))
-        return st;
     uint32_t per_cu = std::max(1u, sv::batch_blocks_per_cu(e.seg_words, e.threads));
     if (c->tuning.wg_per_cu)
         per_cu = std::min(per_cu, c->tuning.wg_per_cu);
@@ -863,16 +875,26 @@ int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s
     k.blocks = per_cu * c->n_cu;
     k.max_intervals = static_cast<uint32_t>(e.counts.bytes / sizeof(unsigned long long));
     k.counts_bytes = e.counts.bytes;
-    k.small = e.small;
-    if (!e.exec || !(e.key == k))
-        if (int st = capture_batch_graph(c, e, k))
-            return st;
+    k.small = small;
+    const int v = small ? 1 : 0;
+    if (!e.exec[v] || !(e.key[v] == k))
+        return capture_batch_graph(c, e, k);
+    return SIEVE_OK;
+}
+
+int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed)
+{
+    const uint32_t n = e.n;
+    if (int st = engine_reserve(c, e, n, e.items))
+        return st;
+    if (int st = engine_graph(c, e, d_words, e.small))
+        return st;
     HIP_TRY(c, hipMemcpyAsync(e.blob.p, e.s_blob.p, e.blob_used, hipMemcpyHostToDevice, s));
     if (timed) {
         c->ev_valid = false;
         HIP_TRY(c, hipEventRecord(c->ev_start, s));
     }
-    HIP_TRY(c, hipGraphLaunch(e.exec, s));
+    HIP_TRY(c, hipGraphLaunch(e.exec[e.small ? 1 : 0], s));
     if (timed) {
         HIP_TRY(c, hipEventRecord(c->ev_stop, s));
         c->ev_valid = true;

@@ -57,9 +57,13 @@ struct BatchEngine {
     std::vector<uint32_t> order;  // intervals in queue order
     std::vector<uint32_t> nmark;
     std::vector<uint64_t> bound;  // isqrt(hi - 1) per interval
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    GraphKey key{};
+    // one captured graph per variant of the marking kernel: [1] for batches
+    // whose marking primes are all below 2^24 (24-bit products), [0] else,
+    // so that batches alternating between the two never re-capture
+    hipGraph_t graph[2] = {};
+    hipGraphExec_t exec[2] = {};
+    GraphKey key[2] = {};
+    uint64_t captures = 0;  // graphs captured and instantiated so far
     hipEvent_t done = nullptr;  // recorded after the last launch
     bool pending = false;       // a launch has been recorded on `done`
     uint32_t n = 0;             // intervals staged
@@ -168,6 +172,14 @@ void engine_free(BatchEngine &e);
 int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
                  uint64_t total_words);
 int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s, bool timed);
+// Capture (if not yet captured for the engine's current buffers and tuning)
+// the graph variant `small` of a batch writing into d_words; runs nothing.
+// Lets a caller capture both variants ahead of time, after a first stage.
+int engine_graph(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, bool small);
+// Words per work item (segment) of a batch on this context's tuning.
+uint32_t batch_seg_words(const sieve_ctx *c);
+// Bytes engine_reserve(n, items) holds on the device.
+uint64_t engine_device_bytes(uint32_t n, uint64_t items);
 hipError_t launch_is_prime(const uint64_t *d_n, uint64_t count, uint8_t *d_out, uint32_t blocks, hipStream_t s);
 hipError_t launch_fermat(const uint64_t *d_n, uint64_t count, const uint64_t *d_draws, uint32_t iterations,
                          uint8_t *d_out, uint32_t blocks, hipStream_t s);

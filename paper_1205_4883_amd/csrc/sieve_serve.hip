@@ -1,24 +1,30 @@
 // Serving loop with continuous batching (declared in sieve.h).
 //
 // One dispatcher thread owns the server's context.  Submitted requests wait
-// in arrival order until their device bytes fit the HBM budget and their
-// returned bitmap fits the pinned host arena (admission).  Whenever a lane
-// (a stream with its own batch engine and device output buffer) is free, the
-// dispatcher packs the admitted requests into one batch, launches its graph,
-// queues the bitmap copies to the requests' host buffers, and records an
-// event; lanes finish independently, so batches overlap on the device while
-// new arrivals form the next batch.  The plain mode serves one request at a
-// time with the plain range launch, for comparison.
+// in arrival order until their bitmap gets a block of the device pool (the
+// HBM budget less the server's fixed device memory, allocated once at
+// creation) and a block of the pinned host arena (admission).  Whenever a
+// lane (a stream with its own batch engine) is free, the dispatcher packs the
+// admitted requests into one batch, launches its graph (captured at
+// creation), queues the bitmap copies to the requests' host blocks, and
+// records an event; lanes finish independently, so batches overlap on the
+// device while new arrivals form the next batch.  The plain mode serves one
+// request at a time with the plain range launch, for comparison.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "buddy.h"
 #include "sieve_runtime.h"
 
 namespace {
@@ -30,81 +36,23 @@ uint64_t now_ns()
                                      .count());
 }
 
-// Pinned host arena with power-of-two size classes (4 KiB .. 2^40 B); freed
-// blocks go back to their class list.  When the arena is carved out and the
-// class list is empty, a block of its own is pinned (and later reused like
-// any other), so an admitted request always gets a buffer.  Not thread-safe:
-// guarded by the server mutex.
-class HostArena {
-  public:
-    int init(size_t bytes)
-    {
-        if (hipHostMalloc(&base_, bytes, hipHostMallocDefault) != hipSuccess) {
-            base_ = nullptr;
-            return SIEVE_ENOMEM;
-        }
-        size_ = bytes;
-        return SIEVE_OK;
-    }
-    ~HostArena()
-    {
-        if (base_)
-            (void)hipHostFree(base_);
-        for (void *p : extra_)
-            (void)hipHostFree(p);
-    }
-    static int cls(size_t bytes)
-    {
-        int c = 12;
-        while ((size_t(1) << c) < bytes)
-            ++c;
-        return c;
-    }
-    static size_t class_bytes(size_t bytes) { return size_t(1) << cls(bytes); }
-    void *alloc(size_t bytes)
-    {
-        const int c = cls(bytes);
-        if (!free_[c].empty()) {
-            void *p = free_[c].back();
-            free_[c].pop_back();
-            return p;
-        }
-        const size_t b = size_t(1) << c;
-        if (used_ + b <= size_) {
-            void *p = static_cast<char *>(base_) + used_;
-            used_ += b;
-            return p;
-        }
-        void *p = nullptr;
-        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess)
-            return nullptr;
-        extra_.push_back(p);
-        return p;
-    }
-    void free(void *p, size_t bytes) { free_[cls(bytes)].push_back(p); }
-    size_t size() const { return size_; }
-
-  private:
-    void *base_ = nullptr;
-    size_t size_ = 0, used_ = 0;
-    std::vector<void *> free_[41];
-    std::vector<void *> extra_;
-};
-
 struct Request {
     uint64_t id = 0, lo = 0, hi = 0, n_words = 0;
     uint32_t flags = 0;
-    uint64_t dev_bytes = 0, host_bytes = 0;
+    uint64_t items = 0;  // batch work items (segments)
     uint64_t t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
     uint64_t pi = 0;
     int status = SIEVE_OK;
-    uint32_t *host = nullptr;  // arena block for the bitmap
+    // a bitmap request holds a device block (its words, from admission until
+    // the copy to the host is done) and a pinned host block (until released)
+    uint64_t dev_off = 0, host_off = 0;
+    int dev_order = -1, host_order = -1;
+    uint32_t *host = nullptr;
 };
 
 struct Lane {
     hipStream_t stream = nullptr;
     sv::BatchEngine eng;
-    uint32_t *d_words = nullptr;  // max_batch_words
     hipEvent_t copied = nullptr;  // after the bitmap copies
     std::vector<Request *> reqs;
     std::vector<sieve_interval> iv;
@@ -123,7 +71,15 @@ struct sieve_server {
     sieve_server_config cfg{};
     sieve_ctx *ctx = nullptr;
     std::vector<Lane> lanes;
-    HostArena arena;
+    // device memory for the bitmaps of admitted requests (the HBM budget
+    // less the server's fixed device memory) and pinned host memory for the
+    // returned bitmaps
+    uint32_t *d_pool = nullptr;
+    sv::Buddy pool;
+    void *h_arena = nullptr;
+    sv::Buddy arena;
+    uint64_t items_cap = 0;        // work items a batch may hold
+    uint64_t captures_at_create = 0;
 
     std::mutex m;
     std::condition_variable cv_work;  // dispatcher: new submissions or stop
@@ -133,7 +89,6 @@ struct sieve_server {
     std::deque<Request *> done;       // finished, not yet polled
     std::unordered_map<uint64_t, Request *> held;  // polled bitmap results, until release
     uint64_t next_id = 1;
-    uint64_t admitted_bytes = 0, admitted_host = 0;
     bool stop = false;
     int fatal = SIEVE_OK;
     sieve_server_stats stats{};
@@ -146,52 +101,81 @@ constexpr uint32_t kDefaultLanes = 3;
 constexpr uint32_t kDefaultMaxBatch = 1024;
 constexpr uint64_t kDefaultBatchWords = 1ull << 26;
 constexpr uint64_t kDefaultArena = 2ull << 30;
+constexpr uint64_t kMinItemsCap = 1ull << 16;
+// Device memory of the server's context that the HBM budget is charged with
+// before its bitmap pool: the full base-prime table (primes below
+// 31,622,777 and their reciprocals, built at creation: 23 MB) with room to
+// build it, and the counter slots.  The plain mode adds the hit-bucket pool
+// of run_range, the batched mode each lane's batch buffers.
+constexpr uint64_t kContextBytes = 64ull << 20;
 
-// Admit from the head of the pending queue while both budgets allow.
+bool wants_words(const Request *r)
+{
+    return (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
+}
+
+// Admit from the head of the pending queue while a device block and a host
+// block can be had for its bitmap (both budgets are real memory: the device
+// pool and the pinned arena).  A request that cannot be placed waits, and so
+// does everything behind it (arrival order).
 void admit_locked(sieve_server *s)
 {
     while (!s->pending.empty()) {
         Request *r = s->pending.front();
-        if (s->admitted_bytes + r->dev_bytes > s->cfg.hbm_budget_bytes ||
-            s->admitted_host + r->host_bytes > s->arena.size()) {
-            ++s->stats.deferred;
-            return;
+        if (wants_words(r)) {
+            const uint64_t bytes = r->n_words * 4;
+            if (!s->pool.alloc(bytes, &r->dev_off, &r->dev_order)) {
+                ++s->stats.deferred;
+                return;
+            }
+            if (!s->arena.alloc(bytes, &r->host_off, &r->host_order)) {
+                s->pool.free(r->dev_off, r->dev_order);
+                r->dev_order = -1;
+                ++s->stats.deferred;
+                return;
+            }
+            r->host = reinterpret_cast<uint32_t *>(static_cast<char *>(s->h_arena) + r->host_off);
         }
-        s->admitted_bytes += r->dev_bytes;
-        s->admitted_host += r->host_bytes;
-        s->stats.peak_admitted_bytes = std::max<uint64_t>(s->stats.peak_admitted_bytes, s->admitted_bytes);
+        s->stats.peak_admitted_bytes = std::max<uint64_t>(s->stats.peak_admitted_bytes, s->pool.used());
+        s->stats.peak_host_bytes = std::max<uint64_t>(s->stats.peak_host_bytes, s->arena.used());
         r->t_admit = now_ns();
         s->pending.pop_front();
         s->admitted.push_back(r);
     }
 }
 
+uint32_t *dev_words(sieve_server *s, const Request *r)
+{
+    return wants_words(r) ? s->d_pool + r->dev_off / 4 : nullptr;
+}
+
+// A request is finished: its device block goes back to the pool (its copy
+// to the host is complete); the host block stays until released.
 void finish_locked(sieve_server *s, Request *r)
 {
-    s->admitted_bytes -= r->dev_bytes;
-    s->admitted_host -= r->host_bytes;
+    if (r->dev_order >= 0) {
+        s->pool.free(r->dev_off, r->dev_order);
+        r->dev_order = -1;
+    }
     r->t_done = now_ns();
     ++s->stats.completed;
     s->done.push_back(r);
 }
 
-// Take admitted requests for one batch (under the lock): host buffers are
-// carved here so that the copies have a destination.
+// Take admitted requests for one batch (under the lock), within the batch's
+// request, word and work-item caps (the lane's buffers and graphs are sized
+// for them at creation, so a batch never re-captures its graph).
 void take_batch_locked(sieve_server *s, Lane &lane)
 {
-    uint64_t words = 0;
+    uint64_t words = 0, items = 0;
     lane.reqs.clear();
     while (!s->admitted.empty() && lane.reqs.size() < s->cfg.max_batch) {
         Request *r = s->admitted.front();
-        const uint64_t w = (r->flags & SIEVE_WANT_BITMAP) ? r->n_words : 0;
-        if (words + w > s->cfg.max_batch_words)
+        const uint64_t w = wants_words(r) ? r->n_words : 0;
+        if (!lane.reqs.empty() && (words + w > s->cfg.max_batch_words || items + r->items > s->items_cap))
             break;
-        if (w) {
-            r->host = static_cast<uint32_t *>(s->arena.alloc(r->host_bytes));
-            if (!r->host)
-                break;  // arena fragmented: wait for releases
-        }
         words += w;
+        items += r->items;
         s->admitted.pop_front();
         lane.reqs.push_back(r);
     }
@@ -205,14 +189,14 @@ int launch_single_lane(sieve_server *s, Lane &lane)
 {
     sieve_ctx *c = s->ctx;
     Request *r = lane.reqs[0];
-    const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
+    uint32_t *d = dev_words(s, r);
     *lane.h_pub = kUnpublished;
     r->t_launch = now_ns();
-    const int st = sv::range_async(c, r->lo, r->hi, bm ? lane.d_words : nullptr, lane.d_pub, lane.stream);
+    const int st = sv::range_async(c, r->lo, r->hi, d, lane.d_pub, lane.stream);
     if (st != SIEVE_OK)
         return st;
-    if (bm)
-        SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
+    if (d)
+        SV_HIP_TRY(c, hipMemcpyAsync(r->host, d, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
     lane.single = true;
     lane.busy = true;
@@ -224,31 +208,26 @@ int launch_batch_lane(sieve_server *s, Lane &lane)
     sieve_ctx *c = s->ctx;
     const uint32_t n = static_cast<uint32_t>(lane.reqs.size());
     lane.iv.resize(n);
-    uint64_t off = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const Request *r = lane.reqs[i];
         sieve_interval &v = lane.iv[i];
         v.lo = r->lo;
         v.hi = r->hi;
-        v.flags = r->flags & SIEVE_WANT_BITMAP;
+        v.flags = wants_words(r) ? SIEVE_WANT_BITMAP : 0;
         v.pad = 0;
-        v.word_offset = v.flags ? off : 0;
-        if (v.flags)
-            off += r->n_words;
+        v.word_offset = v.flags ? r->dev_off / 4 : 0;  // the request's block of the pool
     }
-    if (int st = sv::engine_stage(c, lane.eng, lane.iv.data(), n, lane.d_words, s->cfg.max_batch_words))
+    if (int st = sv::engine_stage(c, lane.eng, lane.iv.data(), n, s->d_pool, s->pool.size() / 4))
         return st;
     const uint64_t t = now_ns();
     for (Request *r : lane.reqs)
         r->t_launch = t;
-    if (int st = sv::engine_launch(c, lane.eng, lane.d_words, lane.stream, false))
+    if (int st = sv::engine_launch(c, lane.eng, s->d_pool, lane.stream, false))
         return st;
-    for (uint32_t i = 0; i < n; ++i) {
-        const Request *r = lane.reqs[i];
-        if ((r->flags & SIEVE_WANT_BITMAP) && r->n_words)
-            SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words + lane.iv[i].word_offset, r->n_words * 4,
-                                         hipMemcpyDeviceToHost, lane.stream));
-    }
+    for (const Request *r : lane.reqs)
+        if (wants_words(r))
+            SV_HIP_TRY(c, hipMemcpyAsync(r->host, dev_words(s, r), r->n_words * 4, hipMemcpyDeviceToHost,
+                                         lane.stream));
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
     lane.single = false;
     lane.busy = true;
@@ -261,12 +240,11 @@ int serve_plain(sieve_server *s, Lane &lane, Request *r)
     sieve_ctx *c = s->ctx;
     r->t_launch = now_ns();
     uint64_t pi = 0;
-    const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
-    if (int st = sv::run_range(c, r->lo, r->hi, bm ? lane.d_words : nullptr, &pi, lane.stream))
+    uint32_t *d = dev_words(s, r);
+    if (int st = sv::run_range(c, r->lo, r->hi, d, &pi, lane.stream))
         return st;
-    if (bm) {
-        SV_HIP_TRY(c, hipMemcpyAsync(r->host, lane.d_words, r->n_words * 4, hipMemcpyDeviceToHost,
-                                     lane.stream));
+    if (d) {
+        SV_HIP_TRY(c, hipMemcpyAsync(r->host, d, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
         SV_HIP_TRY(c, hipStreamSynchronize(lane.stream));
     }
     r->pi = pi;
@@ -321,17 +299,11 @@ void dispatcher(sieve_server *s)
             {
                 std::lock_guard<std::mutex> g(s->m);
                 admit_locked(s);
+                lane.reqs.clear();
                 if (plain) {
-                    lane.reqs.clear();
                     if (!s->admitted.empty()) {
-                        Request *r = s->admitted.front();
-                        const bool bm = (r->flags & SIEVE_WANT_BITMAP) && r->n_words;
-                        if (bm)
-                            r->host = static_cast<uint32_t *>(s->arena.alloc(r->host_bytes));
-                        if (!bm || r->host) {
-                            s->admitted.pop_front();
-                            lane.reqs.push_back(r);
-                        }
+                        lane.reqs.push_back(s->admitted.front());
+                        s->admitted.pop_front();
                     }
                 } else {
                     take_batch_locked(s, lane);
@@ -403,6 +375,14 @@ void dispatcher(sieve_server *s)
     }
 }
 
+uint64_t total_captures(const sieve_server *s)
+{
+    uint64_t n = 0;
+    for (const Lane &lane : s->lanes)
+        n += lane.eng.captures;
+    return n;
+}
+
 }  // namespace
 
 extern "C" {
@@ -434,9 +414,37 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
         delete s;
         return SIEVE_EINVAL;
     }
+    s->items_cap = std::max<uint64_t>(kMinItemsCap, 16ull * s->cfg.max_batch);
+    // The HBM budget is charged with the server's fixed device memory first
+    // (the context and each lane's batch buffers); the rest is the bitmap
+    // pool, allocated here, so that admitted requests never hold more.
+    const bool plain = s->cfg.mode == SIEVE_SERVE_PLAIN;
+    const uint64_t fixed = kContextBytes +
+                           (plain ? sv::kBucketPoolBytes + (1ull << 20)  // run_range's hit buckets
+                                  : s->cfg.lanes * sv::engine_device_bytes(s->cfg.max_batch, s->items_cap));
+    if (s->cfg.hbm_budget_bytes < fixed + (1u << sv::Buddy::kMinOrder)) {
+        delete s;
+        return SIEVE_ENOMEM;
+    }
+    const uint64_t max_block = s->cfg.max_batch_words * 4;
     int st = sieve_create(&s->ctx, hip_device, s->cfg.hbm_budget_bytes);
     if (st == SIEVE_OK)
-        st = s->arena.init(s->cfg.host_arena_bytes);
+        st = sv::ensure_primes(s->ctx, sv::kMaxPrimeLimit);  // no table growth while serving
+    if (st == SIEVE_OK) {
+        const uint64_t pool = s->pool.init(s->cfg.hbm_budget_bytes - fixed, max_block);
+        if (hipMalloc(reinterpret_cast<void **>(&s->d_pool), pool) != hipSuccess) {
+            s->d_pool = nullptr;
+            st = SIEVE_ENOMEM;
+        }
+        s->stats.device_pool_bytes = pool;
+    }
+    if (st == SIEVE_OK) {
+        const uint64_t arena = s->arena.init(s->cfg.host_arena_bytes, max_block);
+        if (arena == 0 || hipHostMalloc(&s->h_arena, arena, hipHostMallocDefault) != hipSuccess) {
+            s->h_arena = nullptr;
+            st = SIEVE_ENOMEM;
+        }
+    }
     s->lanes.resize(s->cfg.lanes);
     for (Lane &lane : s->lanes) {
         if (st != SIEVE_OK)
@@ -444,8 +452,6 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
         hipError_t e = hipStreamCreateWithFlags(&lane.stream, hipStreamNonBlocking);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&lane.copied, hipEventDisableTiming);
-        if (e == hipSuccess)
-            e = hipMalloc(&lane.d_words, s->cfg.max_batch_words * 4);
         void *pub = nullptr;
         if (e == hipSuccess)
             e = hipHostMalloc(&pub, 64, hipHostMallocMapped | hipHostMallocCoherent);
@@ -457,16 +463,28 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
             st = e == hipErrorOutOfMemory ? SIEVE_ENOMEM : SIEVE_EDEVICE;
         if (st == SIEVE_OK)
             st = sv::engine_init(s->ctx, lane.eng);
-        // size the lane's batch buffers up front (a full batch of requests,
-        // each a few segments) so that batches rarely re-capture the graph
+        if (plain)
+            continue;
+        // Size the lane's batch buffers for a full batch and capture both
+        // graph variants now: a capture on the dispatcher thread would stall
+        // every lane in the middle of serving.
         if (st == SIEVE_OK)
-            st = sv::engine_reserve(s->ctx, lane.eng, s->cfg.max_batch, 16ull * s->cfg.max_batch);
+            st = sv::engine_reserve(s->ctx, lane.eng, s->cfg.max_batch, s->items_cap);
+        if (st == SIEVE_OK) {
+            const sieve_interval none{0, 0, 0, 0, 0};
+            st = sv::engine_stage(s->ctx, lane.eng, &none, 1, s->d_pool, s->pool.size() / 4);
+        }
+        if (st == SIEVE_OK)
+            st = sv::engine_graph(s->ctx, lane.eng, s->d_pool, false);
+        if (st == SIEVE_OK)
+            st = sv::engine_graph(s->ctx, lane.eng, s->d_pool, true);
     }
     if (st != SIEVE_OK) {
         s->stop = true;
         sieve_server_destroy(s);
         return st;
     }
+    s->captures_at_create = total_captures(s);
     s->worker = std::thread(dispatcher, s);
     *out = s;
     return SIEVE_OK;
@@ -485,14 +503,10 @@ int sieve_server_submit(sieve_server *s, uint64_t lo, uint64_t hi, uint32_t flag
     r->hi = hi;
     r->flags = flags & SIEVE_WANT_BITMAP;
     r->n_words = sieve_bitmap_words(lo, hi);
-    const bool bm = r->flags && r->n_words;
-    r->dev_bytes = bm ? r->n_words * 4 : 0;
-    r->host_bytes = bm ? HostArena::class_bytes(r->n_words * 4) : 0;
-    if (r->n_words > s->cfg.max_batch_words && bm) {
-        delete r;
-        return SIEVE_ENOMEM;
-    }
-    if (r->dev_bytes > s->cfg.hbm_budget_bytes || r->host_bytes > s->arena.size()) {
+    const uint32_t sw = sv::batch_seg_words(s->ctx);
+    r->items = (r->n_words + sw - 1) / sw;
+    if (wants_words(r) && (r->n_words > s->cfg.max_batch_words || r->n_words * 4 > s->pool.max_block() ||
+                           r->n_words * 4 > s->arena.max_block())) {
         delete r;
         return SIEVE_ENOMEM;
     }
@@ -554,10 +568,10 @@ int sieve_server_release(sieve_server *s, uint64_t id)
     if (it == s->held.end())
         return SIEVE_EINVAL;
     Request *r = it->second;
-    s->arena.free(r->host, r->host_bytes);
+    s->arena.free(r->host_off, r->host_order);
     s->held.erase(it);
     delete r;
-    s->cv_work.notify_one();  // freed host memory may let a batch form
+    s->cv_work.notify_one();  // freed host memory may let a request in
     return SIEVE_OK;
 }
 
@@ -567,6 +581,7 @@ int sieve_server_get_stats(sieve_server *s, sieve_server_stats *out)
         return SIEVE_EINVAL;
     std::lock_guard<std::mutex> g(s->m);
     *out = s->stats;
+    out->graph_captures = total_captures(s) - s->captures_at_create;
     return s->fatal;
 }
 
@@ -584,8 +599,6 @@ int sieve_server_destroy(sieve_server *s)
     for (Lane &lane : s->lanes) {
         if (s->ctx)
             sv::engine_free(lane.eng);
-        if (lane.d_words)
-            (void)hipFree(lane.d_words);
         if (lane.h_pub)
             (void)hipHostFree(const_cast<unsigned long long *>(lane.h_pub));
         if (lane.copied)
@@ -601,6 +614,10 @@ int sieve_server_destroy(sieve_server *s)
         delete r;
     for (Request *r : s->admitted)
         delete r;
+    if (s->d_pool)
+        (void)hipFree(s->d_pool);
+    if (s->h_arena)
+        (void)hipHostFree(s->h_arena);
     if (s->ctx)
         sieve_destroy(s->ctx);
     delete s;
@@ -622,9 +639,13 @@ int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint
     sieve_server *s = nullptr;
     if (int st = sieve_server_create(hip_device, cfg, &s))
         return st;
-    int sub_status = SIEVE_OK;
+    std::atomic<int> sub_status{SIEVE_OK};
+    // Request i is due at t0 + t_arrival_s[i]; its latency is measured from
+    // then, so a submitter that falls behind shows up as queueing delay.
+    const auto t0 = std::chrono::steady_clock::now();
+    const uint64_t t0_ns = static_cast<uint64_t>(
+        std::chrono::duration_cast<std::chrono::nanoseconds>(t0.time_since_epoch()).count());
     std::thread submitter([&] {
-        const auto t0 = std::chrono::steady_clock::now();
         for (uint64_t i = 0; i < n; ++i) {
             const auto due = t0 + std::chrono::nanoseconds(static_cast<int64_t>(t_arrival_s[i] * 1e9));
             // sleep most of the way, then spin for the last stretch
@@ -636,7 +657,7 @@ int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint
             uint64_t id = 0;  // ids are 1, 2, ... in submission order
             const int st = sieve_server_submit(s, lo[i], hi[i], flags[i], &id);
             if (st != SIEVE_OK) {
-                sub_status = st;
+                sub_status.store(st);
                 return;
             }
         }
@@ -654,20 +675,22 @@ int sieve_serve_trace(int hip_device, const sieve_server_config *cfg, const uint
                 status = r.status;
             if (i < n) {
                 pi_out[i] = r.pi;
-                latency_ms_out[i] = (r.t_done_ns - r.t_submit_ns) * 1e-6;
+                const double due_ns = static_cast<double>(t0_ns) + t_arrival_s[i] * 1e9;
+                latency_ms_out[i] = (static_cast<double>(r.t_done_ns) - due_ns) * 1e-6;
             }
             if (r.words)
                 sieve_server_release(s, r.id);
         }
         got += k;
-        if (sub_status != SIEVE_OK)
+        if (sub_status.load() != SIEVE_OK)
             break;
     }
     submitter.join();
     if (stats_out)
         sieve_server_get_stats(s, stats_out);
     sieve_server_destroy(s);
-    return sub_status != SIEVE_OK ? sub_status : status;
+    const int sub = sub_status.load();
+    return sub != SIEVE_OK ? sub : status;
 }
 
 }  // extern "C"

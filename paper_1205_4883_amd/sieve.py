@@ -78,7 +78,8 @@ class sieve_server_stats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("single_launches", ctypes.c_uint64),
                 ("max_batch_seen", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
-                ("peak_admitted_bytes", ctypes.c_uint64)]
+                ("peak_admitted_bytes", ctypes.c_uint64), ("peak_host_bytes", ctypes.c_uint64),
+                ("device_pool_bytes", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64)]
 
 
 INTERVAL_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8"), ("word_offset", "<u8"),

@@ -63,7 +63,11 @@ def test_server_mix_equals_alone_and_oracle(sv, alone, oracle_mod):
         ids = [server.submit(int(a), int(b), bool(f)) for a, b, f in zip(lo, hi, bm)]
         got = _drain(server, len(ids))
         st = server.stats()
-        assert st["completed"] == 300 and st["batches"] >= 1
+        assert st["completed"] == 300
+        # requests were batched, lanes overlapped, and no graph was captured
+        # while serving (both variants are captured when the server starts)
+        assert st["max_batch_seen"] > 1 and st["max_inflight"] >= 2, st
+        assert st["graph_captures"] == 0, st
     finally:
         server.close()
     _check_against_alone(alone, lo, hi, bm, ids, got)
@@ -98,22 +102,85 @@ def test_server_single_requests_take_the_plain_launch(sv, alone, oracle_mod):
         server.close()
 
 
-def test_server_budget_defers_and_stays_exact(sv, alone):
-    # bitmaps of 125 KB .. 1 MB against a 1 MiB budget: admission must wait
+def test_server_budget_binds_device_memory(sv, alone):
+    # The HBM budget is real memory: 64 MiB for the context, each lane's
+    # batch buffers, and the rest as the device pool the admitted bitmaps
+    # live in.  A budget about 10 MiB over the fixed part leaves a pool far
+    # smaller than the 60 bitmaps below (125 KB .. 1 MB each, 34 MB in
+    # all): admission must wait for earlier requests to finish, the pool is
+    # never over-committed, and every result stays exact.
+    import torch
+
+    budget = (64 + 2 + 10) << 20
     rng = np.random.default_rng(5)
     lo = rng.integers(10**9, 10**11, 60).astype(np.uint64)
     hi = lo + rng.integers(2 * 10**6, 16 * 10**6, 60).astype(np.uint64)
     bm = np.ones(60, dtype=bool)
-    server = sv.Server(0, lanes=2, hbm_budget_bytes=1 << 20, host_arena_bytes=1 << 22)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(0)[0]
+    server = sv.Server(0, lanes=2, hbm_budget_bytes=budget, host_arena_bytes=1 << 22)
     try:
+        held = free0 - torch.cuda.mem_get_info(0)[0]
+        print(f"case server budget: {budget} budget, {held} device bytes taken by the server", flush=True)
+        assert held <= budget + (32 << 20)  # the runtime's own stream and queue memory aside
         ids = [server.submit(int(a), int(b), True) for a, b in zip(lo, hi)]
         got = _drain(server, len(ids))
         st = server.stats()
+        assert 0 < st["device_pool_bytes"] <= budget - (64 << 20)
         assert st["deferred"] > 0
-        assert st["peak_admitted_bytes"] <= 1 << 20
+        assert 0 < st["peak_admitted_bytes"] <= st["device_pool_bytes"]
+        assert st["peak_host_bytes"] <= 1 << 22
+        assert st["graph_captures"] == 0
     finally:
         server.close()
     _check_against_alone(alone, lo, hi, bm, ids, got)
+
+
+def test_server_budget_below_the_fixed_memory_is_refused(sv):
+    with pytest.raises(sv.SieveError) as e:
+        sv.Server(0, hbm_budget_bytes=1 << 20)
+    assert e.value.status == sv.sieve.SIEVE_ENOMEM
+
+
+def test_server_staggered_arrivals_equal_alone_and_oracle(sv, alone, oracle_mod):
+    # Requests arrive in waves while earlier ones are on the GPU, including
+    # ranges of the served workload's greatest length (about 1e9 integers,
+    # bitmaps of 62.5 MB); every result equals the same range sieved alone,
+    # word for word, and a sample equals the oracle.
+    rng = np.random.default_rng(41)
+    lo, hi, bm = _requests(43, 96, max_len=1e8)
+    lo = np.concatenate([lo, np.array([10**12 - 10**9 - 12345, 3 * 10**11 + 1, 10**9], dtype=np.uint64)])
+    hi = np.concatenate([hi, np.array([10**12 - 12345, 3 * 10**11 + 1 + 999_999_937, 2 * 10**9],
+                                      dtype=np.uint64)])
+    bm = np.concatenate([bm, np.array([True, True, False])])
+    order = rng.permutation(lo.size)
+    server = sv.Server(0, lanes=3)
+    try:
+        ids, got = {}, {}
+        print(f"case server staggered arrivals ({lo.size} requests)", flush=True)
+        for wave in np.array_split(order, 12):
+            for i in wave:
+                ids[int(i)] = server.submit(int(lo[i]), int(hi[i]), bool(bm[i]))
+            for r in server.results(wait_us=300):
+                got[r["id"]] = r
+        got.update(_drain(server, lo.size - len(got), timeout_s=120))
+        st = server.stats()
+        assert st["completed"] == lo.size and st["graph_captures"] == 0
+        assert st["max_inflight"] >= 2, st
+    finally:
+        server.close()
+    rs = [got[ids[i]] for i in range(lo.size)]
+    # some request was admitted while another was on the device
+    assert any(a["t_admit_ns"] > b["t_launch_ns"] and a["t_admit_ns"] < b["t_done_ns"]
+               for a in rs for b in rs if a["id"] != b["id"])
+    _check_against_alone(alone, lo, hi, bm, [ids[i] for i in range(lo.size)], got)
+    for i in list(range(0, lo.size, 8)) + [lo.size - 3, lo.size - 2, lo.size - 1]:
+        r = got[ids[i]]
+        if bm[i]:
+            want, want_pi = oracle_mod.bitmap(int(lo[i]), int(hi[i]))
+            assert r["pi"] == want_pi and np.array_equal(r["words"], want), i
+        else:
+            assert r["pi"] == oracle_mod.count(int(lo[i]), int(hi[i])), i
 
 
 def test_server_plain_mode_matches(sv, alone):
@@ -160,6 +227,7 @@ def test_serve_trace_batched_equals_plain_and_oracle(sv, oracle_mod):
     pi_p, lat_p, st_p = sv.sieve_serve_trace(0, tr["lo"], tr["hi"], flags, tr["t"],
                                              mode=sv.sieve.SIEVE_SERVE_PLAIN)
     assert st_b["completed"] == n and st_p["completed"] == n
+    assert st_b["graph_captures"] == 0
     assert np.array_equal(pi_b, pi_p)
     assert np.all(lat_b > 0) and np.all(lat_p > 0)
     for i in range(0, n, 100):
