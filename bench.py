@@ -3,24 +3,30 @@
 Default workload: the count-only sieve of [2, 1e10) (pi = 455052511), one
 step = one sieve_range_count call (base primes resident, pre-sieve, dense and
 sparse marking, popcount reduction, count published to pinned memory).
-Prints one JSON line.
+Prints one JSON line.  Besides the headline it carries a block per other
+workload: c1 and c2 (the bitmaps of [2, 1e7) and [2, 1e9)), batch (4096
+intervals in one graph launch, autotuned, against 4096 plain calls), serve
+(the 60 s Poisson trace through the serving loop, batched and plain) and mr
+(batched Miller-Rabin).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Workloads: count-1e10 (default), bitmap-1e9, bitmap-1e7 (one range per
 step), batch-4096 (4096 seeded intervals per sieve_batch call), serve-2000
-(a 60 s Poisson trace through the serving loop), mr-2e24 (Miller-Rabin of
-2^24 random odd 64-bit integers).
+(the 60 s trace), mr-2e24 (Miller-Rabin of 2^24 random odd 64-bit integers).
 
 Throughput is sieved integers per second, (hi - lo) / step time.  The roofline
-object prices the marking kernel's algorithmic LDS work against the chip's LDS
-lane-op peak (256 CUs x 32 banks x 2.4 GHz, one 32-bit access per bank per
-clock).  The work is one 32-bit LDS atomic per crossed-off odd multiple m of
-every base prime 37 <= p <= sqrt(hi-1), max(p^2, lo) <= m < hi (the kernels
-strike 3..31 with periodic pre-sieve tables), plus one LDS write and one read
-per bitmap word; frac_wheel30 prices the larger wheel-30 work (marks from
-p = 7) for comparison.  The cpu_baseline object times the CPU oracle on the
-host over the same range.
+object prices the marking kernel's algorithmic LDS work against the LDS
+atomic-OR rate measured on this device by sieve_measure_peaks (the planning
+figure, 256 CUs x 32 banks x 2.4 GHz, beside it).  The work is one 32-bit LDS
+atomic per crossed-off odd multiple m of every base prime 37 <= p <=
+sqrt(hi-1), max(p^2, lo) <= m < hi (the kernels strike 3..31 with periodic
+pre-sieve tables), plus one LDS write and one read per bitmap word;
+frac_wheel30 prices the larger wheel-30 work (marks from p = 7).  Its `units`
+object gives each unit's use from the committed rocprofv3 counters of the
+same kernel source (VALU issue against the measured VALU peak, LDS busy and
+bank-conflict cycles), and `bound` names the busier one.  The cpu_baseline
+object times the CPU oracle on the host over the same range.
 """
 import argparse
 import hashlib
@@ -51,39 +57,14 @@ LDS_PEAK_LANE_OPS = N_CU * CLOCK_HZ * LDS_LANES_PER_CLK
 HBM_PEAK_BPS = 8.0e12
 
 
-def _active_level(path):
-    """The line marked '*' (the current level) of an amdgpu pp_dpm_* file."""
-    try:
-        with open(path) as f:
-            for line in f:
-                if line.rstrip().endswith("*"):
-                    return line.split(":", 1)[-1].strip(" *\n")
-    except OSError:
-        pass
-    return None
-
-
 def device_info(torch):
-    """Name, architecture and compute-unit count as the runtime reports them,
-    and the active shader and memory clock levels read from the device's PCI
-    sysfs node (no helper program is started: under a profiler every child
-    process would inherit its preloaded library).  The shader level is the
-    power controller's running average, which includes idle time, so right
-    after a short timed loop it reads well below the clock the kernels ran
-    at."""
+    """Name, architecture and compute-unit count as the runtime reports them.
+    The shader clock the kernels ran at is in `peaks` (measured by the
+    microbenchmarks' own cycle and wall counters) and in the roofline's
+    units (kernel cycles from the committed counters over the kernel time)."""
     props = torch.cuda.get_device_properties(0)
-    info = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+    return {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
             "compute_units": props.multi_processor_count}
-    try:
-        node = "/sys/bus/pci/devices/%04x:%02x:%02x.0" % (
-            props.pci_domain_id, props.pci_bus_id, props.pci_device_id)
-    except AttributeError:
-        return info
-    for key, fname in (("sclk_running_avg", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk")):
-        level = _active_level(os.path.join(node, fname))
-        if level:
-            info[key] = level
-    return info
 
 
 def host_info(threads):
@@ -124,6 +105,32 @@ def _odd_multiples(p, lo, hi):
     return np.maximum(odd_upto(jhi) - odd_upto(jlo - 1), 0)
 
 
+# Multipliers m prime to 30: the wheel the marking kernels walk (3 | m or
+# 5 | m is struck by the pre-sieve).  _WHEEL_UPTO[r] = such m in [1, r].
+_WHEEL = (1, 7, 11, 13, 17, 19, 23, 29)
+_WHEEL_UPTO = [sum(1 for w in _WHEEL if w <= r) for r in range(30)]
+
+
+def _wheel_multiples(p, lo, hi):
+    """Per prime p: the multiples p*m, m prime to 30, with max(p^2, lo) <= p*m
+    < hi -- the LDS atomics the marking kernels issue for p."""
+    import numpy as np
+
+    def upto(x):  # multipliers prime to 30 in [1, x]
+        x = np.maximum(x, 0)
+        return 8 * (x // 30) + np.asarray(_WHEEL_UPTO, dtype=np.int64)[x % 30]
+
+    a = np.maximum(p * p, lo)
+    mhi = (hi - 1) // p
+    mlo = -(-a // p)
+    return np.maximum(upto(mhi) - upto(mlo - 1), 0)
+
+
+# LDS accesses per bitmap word besides the marks: the pre-sieve's three
+# table reads and its store, and the count's read.
+ISSUED_OPS_PER_WORD = 5
+
+
 def algorithmic_lds_ops(primes, lo, hi, pmin=FIRST_MARKED_PRIME):
     """Marks (odd multiples m of each base prime pmin <= p <= isqrt(hi-1) with
     max(p^2, lo) <= m < hi) plus two LDS accesses per bitmap word (the
@@ -151,7 +158,8 @@ def lds_roofline(primes, ranges, seconds):
     p = p[p >= 7]
     n_pre = int(np.searchsorted(p, FIRST_MARKED_PRIME))  # 7..31, struck by the pre-sieve
     marks = marks30 = words = 0
-    for lo, hi in ranges:
+    ranges_list = [(int(a), int(b)) for a, b in ranges]
+    for lo, hi in ranges_list:
         if hi <= lo:
             continue
         k = int(np.searchsorted(p, math.isqrt(hi - 1), side="right")) if hi > 1 else 0
@@ -161,14 +169,34 @@ def lds_roofline(primes, ranges, seconds):
         marks += m30 - int(per[:n_pre].sum())
         words += (hi // 2 - lo // 2 + 31) // 32
     lane_ops, lane_ops30 = marks + 2 * words, marks30 + 2 * words
+    issued = issued_marks(p[n_pre:], ranges_list)
+    issued_ops = issued + ISSUED_OPS_PER_WORD * words
     achieved = lane_ops / seconds
     return {
         "bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
         "unit": "Glane-op/s", "frac": achieved / LDS_PEAK_LANE_OPS,
         "frac_wheel30": lane_ops30 / seconds / LDS_PEAK_LANE_OPS,
+        "issued_frac": issued_ops / seconds / LDS_PEAK_LANE_OPS,
         "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": words,
                             "first_marked_prime": FIRST_MARKED_PRIME,
-                            "marks_wheel30": marks30, "lds_lane_ops_wheel30": lane_ops30}}
+                            "marks_wheel30": marks30, "lds_lane_ops_wheel30": lane_ops30,
+                            "issued_marks": issued, "issued_lds_lane_ops": issued_ops}}
+
+
+def issued_marks(p, ranges):
+    """The LDS atomics the marking kernels issue: multiples p*m with m prime
+    to 30, from max(p^2, lo), for the marking primes p (>= 37) of each range."""
+    import math
+
+    import numpy as np
+
+    total = 0
+    for lo, hi in ranges:
+        if hi <= lo:
+            continue
+        k = int(np.searchsorted(p, math.isqrt(hi - 1), side="right")) if hi > 1 else 0
+        total += int(_wheel_multiples(p[:k], lo, hi).sum())
+    return total
 
 
 def kernel_source_hash():
@@ -192,10 +220,130 @@ def load_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_batch(sv, torch, s, steps, warmup, check_plain=True):
+def load_counters(workload):
+    """Per-dispatch rocprofv3 counters of the workload's dominant kernel from
+    the committed profile, if taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec
+
+
+def unit_use(counters, peaks, n_cu, kernel_ms):
+    """Each unit's use during the kernel from its counters: VALU issue
+    (wave-instructions per clock per CU) against the measured VALU peak, and
+    the fraction of cycles the LDS was busy (and how much of that was bank
+    conflicts).  `bound` is the busier unit."""
+    if not counters:
+        return None, {"note": "no counters for the current kernel source"}
+    c = counters["per_dispatch"]
+    cycles = c["GRBM_GUI_ACTIVE"] / 8.0  # the counter sums the eight XCDs
+    valu_clk = c["SQ_INSTS_VALU"] / n_cu / cycles
+    valu_peak = peaks["valu_wave_instr_per_clk_cu"] if peaks else 1.0
+    lds_busy = c["SQ_LDS_IDX_ACTIVE"] / n_cu / cycles
+    units = {
+        "valu": {"wave_instr_per_clk_cu": valu_clk, "peak_per_clk_cu": valu_peak,
+                 "frac": valu_clk / valu_peak, "instr_per_dispatch": c["SQ_INSTS_VALU"]},
+        "lds": {"busy_frac": lds_busy,
+                "bank_conflict_share_of_busy": c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"],
+                "instr_per_dispatch": c["SQ_INSTS_LDS"]},
+        "kernel_clock_hz_from_counters": cycles / (counters["kernel_ns_avg"] * 1e-9),
+        "counters_kernel_ms": counters["kernel_ns_avg"] * 1e-6,
+        "source": f"profiles/counters_{counters['workload']}.json",
+    }
+    bound = "valu" if units["valu"]["frac"] > lds_busy else "lds"
+    return bound, units
+
+
+def measured_roofline(primes, ranges, seconds, peaks, counters, workload_key, kernel_name):
+    """lds_roofline against the measured LDS atomic-OR peak (planning peak
+    beside it), with the units' use from the counters and the binding unit."""
+    roof = lds_roofline(primes, ranges, seconds)
+    if peaks:
+        measured = peaks["lds_or_lane_ops_per_s"]
+        roof["frac_planning_peak"] = roof["frac"]
+        roof["peak_planning"] = roof["peak"]
+        roof["peak"] = measured / 1e9
+        roof["frac"] = roof["achieved"] * 1e9 / measured
+        roof["frac_wheel30"] = roof["frac_wheel30"] * LDS_PEAK_LANE_OPS / measured
+        roof["issued_frac"] = roof["issued_frac"] * LDS_PEAK_LANE_OPS / measured
+        roof["peak_source"] = "measured: conflict-free ds_or_b32 on every CU (sieve_measure_peaks)"
+    bound, units = unit_use(counters, peaks, N_CU, seconds * 1e3)
+    roof["bound"] = bound or "lds"
+    roof["units"] = units
+    roof["traffic"] = load_traffic(workload_key)
+    roof["kernel"] = kernel_name
+    return roof
+
+
+def run_single(sv, torch, s, wl, steps, warmup, peaks, workload_key, latency_calls=0):
+    """One range per step: kernel time from HIP events (timing on), then the
+    call time as production uses it (timing off).  Returns the record."""
+    import numpy as np
+
+    lo, hi = wl["lo"], wl["hi"]
+    stream = torch.cuda.current_stream(0)
+    out = s.alloc_words(lo, hi) if wl["bitmap"] else None
+
+    def step():
+        if out is None:
+            return sv.sieve_range_count(s.ctx, lo, hi, stream=stream)
+        return sv.sieve_range_bitmap(s.ctx, lo, hi, out, out.numel(), True, stream=stream)
+
+    sv.sieve_set_timing(s.ctx, True)
+    t_cold = time.perf_counter()
+    assert step() == wl["pi"]  # cold: base primes beyond the context's table, plans
+    torch.cuda.synchronize()
+    cold_ms = 1e3 * (time.perf_counter() - t_cold)
+    for _ in range(warmup):
+        assert step() == wl["pi"]
+    kernel_ms = []
+    for _ in range(max(steps, 20)):
+        assert step() == wl["pi"]
+        kernel_ms.append(sv.sieve_last_kernel_ms(s.ctx))
+    sv.sieve_set_timing(s.ctx, False)  # calls as in production, no events
+    torch.cuda.synchronize()
+    n_calls = max(steps, latency_calls)
+    call_ms = []
+    t0 = time.perf_counter()
+    for _ in range(n_calls):
+        tc = time.perf_counter()
+        pi = step()
+        call_ms.append(1e3 * (time.perf_counter() - tc))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n_calls
+    assert pi == wl["pi"], pi
+    primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(hi)) + 1)
+    k_ms = float(np.mean(kernel_ms))
+    plan = sv.sieve_plan(lo, hi, tuning=s.tuning())
+    roof = measured_roofline(primes, [(lo, hi)], k_ms * 1e-3, peaks, load_counters(workload_key),
+                             workload_key, "range_kernel<write=%s>" % ("true" if wl["bitmap"] else "false"))
+    roof.update({"kernel_ms": k_ms, "kernel_ms_min": float(np.min(kernel_ms))})
+    if wl["bitmap"]:
+        words = roof["work_per_launch"]["words"]
+        roof["hbm_write_GBps"] = 4 * words / (k_ms * 1e-3) / 1e9
+        roof["hbm_write_frac"] = roof["hbm_write_GBps"] * 1e9 / HBM_PEAK_BPS
+    return {
+        "workload": wl["name"], "lo": lo, "hi": hi, "pi": pi, "calls": n_calls,
+        "ms_per_call": 1e3 * dt, "ints_per_s": (hi - lo) / dt, "cold_ms": cold_ms,
+        "call_ms": {"p50": float(np.percentile(call_ms, 50)), "min": float(np.min(call_ms)),
+                    "p99": float(np.percentile(call_ms, 99)), "max": float(np.max(call_ms))},
+        "plan": {k: plan[k] for k in ("seg_bits", "dense_limit", "block_threads", "n_segments")},
+        "roofline": roof,
+    }
+
+
+def run_batch(sv, torch, s, steps, warmup, check_plain=True, tune=True, peaks=None):
     """The batched workload: 4096 seeded intervals, per-interval pi and packed
     bitmaps from one sieve_batch call (one graph launch), against the same
-    intervals sieved one sieve_range_bitmap call at a time on one stream."""
+    intervals sieved one sieve_range_bitmap call at a time on one stream.
+    With tune, sieve_autotune picks the segment size, dense bound and
+    workgroups per CU on these intervals (bitmaps included) first and the
+    context keeps its choice; the automatic plan is one of its candidates."""
     import numpy as np
 
     from paper_1205_4883_amd import workloads
@@ -210,9 +358,20 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
     iv["lo"], iv["hi"], iv["word_offset"], iv["flags"] = los, his, offs, 1
     words = torch.empty(total, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream(0)
+    sv.sieve_set_timing(s.ctx, True)
     t_cold = time.perf_counter()
     pi = sv.sieve_batch(s.ctx, iv, words, total, stream=stream)  # cold: graph capture, prime table
     cold_ms = 1e3 * (time.perf_counter() - t_cold)
+    tuning = None
+    if tune:
+        t_tune = time.perf_counter()
+        best, best_ms = sv.sieve_autotune(s.ctx, iv, apply=True)
+        tuning = {"chosen": best, "tuner_kernel_ms": best_ms,
+                  "tune_s": time.perf_counter() - t_tune,
+                  "note": "sieve_autotune on these 4096 intervals with their bitmaps; "
+                          "candidates: the automatic plan, 4 segment sizes x 3 dense bounds, "
+                          "then 1 or 2 workgroups per CU"}
+        pi = sv.sieve_batch(s.ctx, iv, words, total, stream=stream)  # graph for the chosen tuning
     for _ in range(warmup):
         pi = sv.sieve_batch(s.ctx, iv, words, total, stream=stream)
     torch.cuda.synchronize()
@@ -233,16 +392,17 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
            "intervals": n, "integers": ints, "bitmap_bytes": 4 * total,
            "inputs_sha256": workloads.fingerprint(los, his),
            "ms_per_batch": 1e3 * t_batch, "graph_ms": float(np.mean(kms)), "cold_ms": cold_ms,
-           "ints_per_s": ints / t_batch, "pi_sum": int(pi.sum())}
+           "ints_per_s": ints / t_batch, "pi_sum": int(pi.sum()), "tuning": tuning}
     rec["_pi"] = pi
     # roofline of the batch graph (reset, batch kernel, reduction, counts
     # copy; the batch kernel dominates): the intervals' algorithmic LDS work
     # over the graph's event-timed duration
     primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(float(his.max()))) + 2)
     g_ms = rec["graph_ms"]
-    roof = lds_roofline(primes, zip(los.tolist(), his.tolist()), g_ms * 1e-3)
-    roof.update({"traffic": load_traffic("batch-4096"),
-                 "kernel": "batch graph (batch_kernel dominant)", "kernel_ms": g_ms})
+    roof = measured_roofline(primes, zip(los.tolist(), his.tolist()), g_ms * 1e-3, peaks,
+                             load_counters("batch-4096"), "batch-4096",
+                             "batch graph (batch_kernel dominant)")
+    roof["kernel_ms"] = g_ms
     rec["roofline"] = roof
     if check_plain:
         # the same outputs, one plain call per interval (pi returned per call),
@@ -267,8 +427,8 @@ def run_batch(sv, torch, s, steps, warmup, check_plain=True):
 
 def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
     """Replay the served workload (Poisson arrivals, seed 1) for `seconds`
-    through the native server in each mode; latency is arrival to result on
-    the host."""
+    through the native server in each mode; latency runs from each request's
+    scheduled arrival to its result in host memory."""
     import numpy as np
 
     from paper_1205_4883_amd import workloads
@@ -280,8 +440,9 @@ def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
                        "lo log-uniform in [1e3, 1e12], length log-uniform in [1e3, 1e9], "
                        "50% bitmap-return; 32 GiB HBM budget",
            "requests": int(tr["t"].size), "integers": ints,
+           "bitmap_bytes": int(4 * ((tr["hi"] // 2 - tr["lo"] // 2 + 31) // 32)[tr["bitmap"]].sum()),
            "inputs_sha256": workloads.fingerprint(tr["lo"], tr["hi"])}
-    pis = {}
+    pis, lats = {}, {}
     for mode in modes:
         m = sv.sieve.SIEVE_SERVE_PLAIN if mode == "plain" else sv.sieve.SIEVE_SERVE_BATCHED
         pi, lat, st = sv.sieve_serve_trace(0, tr["lo"], tr["hi"], flags, tr["t"], mode=m)
@@ -291,11 +452,19 @@ def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
                      "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
                      "ints_per_s": ints / span, "batches": st["batches"],
                      "max_batch": st["max_batch_seen"], "max_inflight": st["max_inflight"],
-                     "single_launches": st["single_launches"]}
-        pis[mode] = pi
+                     "single_launches": st["single_launches"], "deferred": st["deferred"],
+                     "graph_captures": st["graph_captures"], "device_pool_bytes": st["device_pool_bytes"],
+                     "peak_admitted_bytes": st["peak_admitted_bytes"]}
+        pis[mode], lats[mode] = pi, lat
     if len(pis) == 2:
         assert np.array_equal(pis["batched"], pis["plain"]), "served results differ by mode"
         out["results_equal_across_modes"] = True
+    # the slowest requests of the first mode, with what they asked for
+    m0 = modes[0]
+    slow = np.argsort(lats[m0])[-5:][::-1]
+    out["slowest"] = [{"i": int(i), "t_s": float(tr["t"][i]), "lo": int(tr["lo"][i]),
+                       "len": int(tr["hi"][i] - tr["lo"][i]), "bitmap": bool(tr["bitmap"][i]),
+                       **{f"{m}_ms": float(lats[m][i]) for m in lats}} for i in slow]
     return out
 
 
@@ -456,17 +625,19 @@ def main():
         print(json.dumps({
             "metric": METRIC, "value": r["batched"]["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": 1e3 * secs, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": r["workload"]}, "serve": r}), flush=True)
         return
 
+    s = sv.Sieve(0)
+    peaks = sv.sieve_measure_peaks(s.ctx)  # this device's LDS and VALU rates, measured
+    if args.seg_bits or args.dense_limit or args.block_threads or args.bucket_limit:
+        s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads,
+                 bucket_limit=args.bucket_limit)
+
     if args.workload == "batch-4096":
-        s = sv.Sieve(0)
-        sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
-        if args.seg_bits or args.dense_limit or args.block_threads or args.bucket_limit:
-            s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit,
-                     block_threads=args.block_threads, bucket_limit=args.bucket_limit)
-        b = run_batch(sv, torch, s, args.steps, args.warmup, check_plain=not args.no_plain)
+        b = run_batch(sv, torch, s, args.steps, args.warmup, check_plain=not args.no_plain,
+                      tune=not (args.seg_bits or args.dense_limit or args.block_threads), peaks=peaks)
         s.close()
         pi = b.pop("_pi")
         if not args.no_cpu:
@@ -474,84 +645,51 @@ def main():
         print(json.dumps({
             "metric": METRIC, "value": b["ints_per_s"], "unit": "ints/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_batch"],
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-            "data": "synthetic", "config": {"workload": b["workload"]}, "batch": b}), flush=True)
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+            "data": "synthetic", "config": {"workload": b["workload"]}, "peaks": peaks,
+            "batch": b}), flush=True)
         return
 
     wl = WORKLOADS[args.workload]
     lo, hi = wl["lo"], wl["hi"]
-    s = sv.Sieve(0)
-    sv.sieve_set_timing(s.ctx, True)  # HIP events around each launch, for the roofline
-    if args.seg_bits or args.dense_limit or args.block_threads or args.bucket_limit:
-        s.tuning(seg_bits=args.seg_bits, dense_limit=args.dense_limit, block_threads=args.block_threads,
-                 bucket_limit=args.bucket_limit)
-    stream = torch.cuda.current_stream(0)
-    out = s.alloc_words(lo, hi) if wl["bitmap"] else None
-
-    def step():
-        if out is None:
-            return sv.sieve_range_count(s.ctx, lo, hi, stream=stream)
-        return sv.sieve_range_bitmap(s.ctx, lo, hi, out, out.numel(), True, stream=stream)
-
-    t_cold = time.perf_counter()
-    assert step() == wl["pi"]  # cold: the first call (base primes beyond the context's table, plans)
-    torch.cuda.synchronize()
-    cold_ms = 1e3 * (time.perf_counter() - t_cold)
-    for _ in range(args.warmup):
-        assert step() == wl["pi"]
-    torch.cuda.synchronize()
-    kernel_ms, call_ms = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        tc = time.perf_counter()
-        pi = step()
-        call_ms.append(1e3 * (time.perf_counter() - tc))
-        kernel_ms.append(sv.sieve_last_kernel_ms(s.ctx))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    device = device_info(torch)  # clock levels right after the timed loop
-    assert pi == wl["pi"], pi
-    ms_per_step = 1e3 * dt / args.steps
-    value = (hi - lo) / (dt / args.steps)
-
-    primes = sv.sieve_base_primes(s.ctx, int(np.sqrt(hi)) + 1)
-    k_ms = float(np.mean(kernel_ms))
-    plan = sv.sieve_plan(lo, hi, tuning=s.tuning())
-    roof = lds_roofline(primes, [(lo, hi)], k_ms * 1e-3)
-    words = roof["work_per_launch"]["words"]
-    roof.update({"traffic": load_traffic(args.workload),
-                 "kernel": "range_kernel<write=%s>" % ("true" if wl["bitmap"] else "false"),
-                 "kernel_ms": k_ms, "kernel_ms_min": float(np.min(kernel_ms))})
-    if wl["bitmap"]:
-        roof["hbm_write_GBps"] = 4 * words / (k_ms * 1e-3) / 1e9
+    r = run_single(sv, torch, s, wl, args.steps, args.warmup, peaks, args.workload,
+                   latency_calls=1000 if args.workload == "bitmap-1e7" else 0)
+    device = device_info(torch)
+    plan = r["plan"]
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": r["ints_per_s"],
         "unit": "ints/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r["calls"],
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_call"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        # u64 segment bases and offsets above 2^32, 32-bit words and marks
+        "dtype": "u64" if hi > 1 << 32 else "u32",
         "data": "synthetic",
-        "cold_ms": cold_ms,
-        "call_ms": {"p50": float(np.percentile(call_ms, 50)), "min": float(np.min(call_ms)),
-                    "max": float(np.max(call_ms))},
+        "cold_ms": r["cold_ms"],
+        "call_ms": r["call_ms"],
         "device": device,
-        "config": {"workload": wl["name"], "lo": lo, "hi": hi, "pi": pi,
-                   "presieve_primes": PRESIEVE_PRIMES,
-                   "seg_bits": plan["seg_bits"], "dense_limit": plan["dense_limit"],
-                   "block_threads": plan["block_threads"], "n_segments": plan["n_segments"]},
-        "roofline": roof,
+        "config": {"workload": wl["name"], "lo": lo, "hi": hi, "pi": r["pi"],
+                   "presieve_primes": PRESIEVE_PRIMES, **plan},
+        "roofline": r["roofline"],
+        "peaks": peaks,
     }
     if args.workload == "count-1e10" and not args.no_batch:
-        rec["batch"] = run_batch(sv, torch, s, steps=20, warmup=5)
+        # the other configurations, each in a block of its own
+        for key in ("bitmap-1e7", "bitmap-1e9"):
+            w = WORKLOADS[key]
+            rec["c1" if key == "bitmap-1e7" else "c2"] = run_single(
+                sv, torch, s, w, 200 if key == "bitmap-1e9" else 100, 50, peaks, key,
+                latency_calls=1000 if key == "bitmap-1e7" else 0)
+        rec["batch"] = run_batch(sv, torch, s, steps=20, warmup=5, peaks=peaks)
     s.close()
     if args.workload == "count-1e10" and not args.no_batch:
-        rec["serve"] = run_serve(sv, args.serve_seconds or 5.0)
+        rec["serve"] = run_serve(sv, args.serve_seconds or 60.0)
+        rec["serve"]["load_sweep"] = [run_serve(sv, 2.0, rate=20000.0)]
         rec["mr"] = run_mr(sv, torch, steps=20, warmup=5)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(lo, hi, wl["pi"], bitmap=wl["bitmap"])

@@ -291,7 +291,9 @@ SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t c
  * one or two resident workgroups per CU, and, for a single range that uses
  * hit buckets, a large-prime threshold of 2x or 4x the segment size, or no
  * buckets.  One interval is timed as sieve_range_count, several as a
- * count-only sieve_batch.  Results are cached per context by (single range
+ * sieve_batch in which the intervals that set SIEVE_WANT_BITMAP write their
+ * bitmaps (at their word_offset, into a scratch device buffer the tuner
+ * allocates for the batch's extent and frees before returning).  Results are cached per context by (single range
  * or batch, decade of the largest hi, log2 of the total bitmap words); a
  * cached answer is returned without timing unless SIEVE_TUNE_FORCE is set.
  * With SIEVE_TUNE_APPLY the context keeps the winner; otherwise its tuning
@@ -301,6 +303,35 @@ SIEVE_API int sieve_fermat_batch(sieve_ctx *ctx, const uint64_t *d_n, uint64_t c
 #define SIEVE_TUNE_FORCE 2u
 SIEVE_API int sieve_autotune(sieve_ctx *ctx, const sieve_interval *iv, uint32_t n, uint32_t flags,
                              sieve_tuning *best, double *best_ms);
+
+/* Measured peaks of the two units the sieve kernels load, on this device.
+ * The crossing-off of the paper's sieve (Section 3.1) is one 32-bit LDS
+ * atomic OR per marked multiple, and the segment kernels' address and
+ * start arithmetic runs on the int32 vector ALU (VALU), so the speed of
+ * light of a launch is set by these two rates (the paper frames speedup
+ * against such limits in Section 2.2, Eq. 1-2).  Each rate comes from a
+ * small bounded kernel on every CU (two 1024-thread workgroups per CU, as
+ * the sieve kernels run), timed with HIP events after one warm-up launch.
+ * The shader clock during a kernel is measured from its own cycle and wall
+ * counters. */
+typedef struct sieve_peaks {
+    double lds_or_lane_ops_per_s;         /* ds_or_b32, each half-wavefront on 32 distinct banks */
+    double lds_or_lanes_per_clk_cu;       /* the same per CU per shader clock */
+    double lds_write_lane_ops_per_s;      /* ds_write_b32, same addresses */
+    double lds_or_scatter_lane_ops_per_s; /* ds_or_b32 at random words of 64 KiB */
+    double lds_read_lane_ops_per_s;       /* ds_read_b32, conflict-free */
+    double lds_write_b64_bytes_per_s;     /* ds_write_b64, conflict-free, in bytes */
+    double valu_wave_instr_per_s;         /* int32 add/xor wavefront instructions */
+    double valu_wave_instr_per_clk_cu;    /* the same per CU per shader clock */
+    double lds_or_clock_hz;               /* shader clock during the ds_or_b32 kernel */
+    double valu_clock_hz;                 /* shader clock during the VALU kernel */
+    uint32_t n_cu;
+    uint32_t pad;
+} sieve_peaks;
+
+/* Run the microbenchmarks on the context's device (about 20 ms).  Errors:
+ * SIEVE_EINVAL (NULL arguments), SIEVE_EDEVICE. */
+SIEVE_API int sieve_measure_peaks(sieve_ctx *ctx, sieve_peaks *out);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.

@@ -9,7 +9,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsieve.so")
 SOURCES = ["sieve_kernels.hip", "sieve_api.hip", "sieve_serve.hip", "sieve_primality.hip",
-           "sieve_noalloc.hip"]
+           "sieve_noalloc.hip", "sieve_peaks.hip"]
 
 
 def hipcc_command(out):

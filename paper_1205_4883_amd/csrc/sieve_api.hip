@@ -1216,11 +1216,23 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
             cands.push_back(t);
         }
     }
+    // A batch is timed as the caller will run it: intervals that want their
+    // bitmap write it, into a scratch buffer of the batch's extent.
+    uint64_t extent = 0;
+    for (uint32_t i = 0; i < n && n > 1; ++i)
+        if (iv[i].flags & SIEVE_WANT_BITMAP)
+            extent = std::max(extent, iv[i].word_offset + sieve_bitmap_words(iv[i].lo, iv[i].hi));
+    uint32_t *d_scratch = nullptr;
+    if (extent) {
+        SV_HIP_TRY(c, hipSetDevice(c->device));
+        const hipError_t e = hipMalloc(&d_scratch, extent * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            c->last_hip = e;
+            return SIEVE_ENOMEM;
+        }
+    }
     const bool saved_timing = c->timing;
     c->timing = true;  // candidates are ranked by their kernel times
-    std::vector<sieve_interval> count_only(iv, iv + n);
-    for (auto &v : count_only)
-        v.flags = 0;
     sieve_tuning win{};
     double win_ms = 1e300;
     int st = SIEVE_OK;
@@ -1233,7 +1245,7 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
                 st = sv::run_range(c, iv[0].lo, iv[0].hi, nullptr, &pi, c->stream);
             } else {
                 std::vector<uint64_t> pi(n);
-                st = sieve_batch(c, count_only.data(), n, nullptr, 0, pi.data(), nullptr);
+                st = sieve_batch(c, iv, n, d_scratch, extent, pi.data(), nullptr);
             }
             double k = 0;
             if (st == SIEVE_OK && rep > 0 && sieve_last_kernel_ms(c, &k) == SIEVE_OK)
@@ -1275,6 +1287,10 @@ int sieve_autotune(sieve_ctx *c, const sieve_interval *iv, uint32_t n, uint32_t 
         time_it(t);
         if (st != SIEVE_OK)
             break;
+    }
+    if (d_scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d_scratch);
     }
     c->tuning = saved;
     c->timing = saved_timing;

@@ -478,6 +478,16 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
             st = sv::engine_graph(s->ctx, lane.eng, s->d_pool, false);
         if (st == SIEVE_OK)
             st = sv::engine_graph(s->ctx, lane.eng, s->d_pool, true);
+        // Launch each graph once on the lane's stream with the empty batch:
+        // a graph's first launch uploads it to the device, a cost that does
+        // not belong in the middle of serving.
+        for (int v = 0; v < 2 && st == SIEVE_OK; ++v) {
+            lane.eng.small = v == 1;
+            st = sv::engine_launch(s->ctx, lane.eng, s->d_pool, lane.stream, false);
+            if (st == SIEVE_OK && hipStreamSynchronize(lane.stream) != hipSuccess)
+                st = SIEVE_EDEVICE;
+            lane.eng.pending = false;
+        }
     }
     if (st != SIEVE_OK) {
         s->stop = true;

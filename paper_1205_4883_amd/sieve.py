@@ -30,7 +30,7 @@ EXPORTED = [
     "sieve_get_tuning", "sieve_set_tuning", "sieve_plan", "sieve_bitmap_words",
     "sieve_base_primes", "sieve_range_count", "sieve_range_bitmap", "sieve_batch",
     "sieve_range_bitmap_noalloc",
-    "sieve_autotune", "sieve_is_prime_batch", "sieve_fermat_batch",
+    "sieve_autotune", "sieve_is_prime_batch", "sieve_fermat_batch", "sieve_measure_peaks",
     "sieve_server_create", "sieve_server_submit", "sieve_server_poll", "sieve_server_release",
     "sieve_server_get_stats", "sieve_server_destroy", "sieve_serve_trace",
 ]
@@ -56,6 +56,16 @@ class sieve_interval(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64),
                 ("word_offset", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32)]
+
+
+class sieve_peaks(ctypes.Structure):
+    _fields_ = [("lds_or_lane_ops_per_s", ctypes.c_double), ("lds_or_lanes_per_clk_cu", ctypes.c_double),
+                ("lds_write_lane_ops_per_s", ctypes.c_double),
+                ("lds_or_scatter_lane_ops_per_s", ctypes.c_double),
+                ("lds_read_lane_ops_per_s", ctypes.c_double), ("lds_write_b64_bytes_per_s", ctypes.c_double),
+                ("valu_wave_instr_per_s", ctypes.c_double), ("valu_wave_instr_per_clk_cu", ctypes.c_double),
+                ("lds_or_clock_hz", ctypes.c_double), ("valu_clock_hz", ctypes.c_double),
+                ("n_cu", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class sieve_server_config(ctypes.Structure):
@@ -126,6 +136,7 @@ def _lib():
     lib.sieve_range_bitmap_noalloc.argtypes = [vp, u64, u64, vp, u64, vp, vp]
     lib.sieve_is_prime_batch.argtypes = [vp, vp, u64, vp, vp]
     lib.sieve_fermat_batch.argtypes = [vp, vp, u64, vp, u32, vp, vp]
+    lib.sieve_measure_peaks.argtypes = [vp, ctypes.POINTER(sieve_peaks)]
     lib.sieve_autotune.argtypes = [vp, vp, u32, u32, ctypes.POINTER(sieve_tuning),
                                     ctypes.POINTER(ctypes.c_double)]
     lib.sieve_server_create.argtypes = [i32, ctypes.POINTER(sieve_server_config), ctypes.POINTER(vp)]
@@ -271,17 +282,28 @@ def sieve_fermat_batch(ctx, d_n, count, d_draws, iterations, d_out, stream=None)
            "sieve_fermat_batch")
 
 
+def sieve_measure_peaks(ctx):
+    """Measured LDS and VALU peaks of the context's device (a dict)."""
+    pk = sieve_peaks()
+    _check(_lib().sieve_measure_peaks(ctx, ctypes.byref(pk)), "sieve_measure_peaks")
+    return {k: getattr(pk, k) for k, _ in sieve_peaks._fields_ if k != "pad"}
+
+
 SIEVE_TUNE_APPLY = 1
 SIEVE_TUNE_FORCE = 2
 
 
-def sieve_autotune(ctx, los, his, apply=True, force=False):
-    """Time candidate tunings on the ranges [los[i], his[i]); returns
-    (tuning dict, kernel ms of the winner)."""
-    los = np.atleast_1d(np.asarray(los, dtype=np.uint64))
-    his = np.atleast_1d(np.asarray(his, dtype=np.uint64))
-    iv = np.zeros(len(los), dtype=INTERVAL_DTYPE)
-    iv["lo"], iv["hi"] = los, his
+def sieve_autotune(ctx, los, his=None, apply=True, force=False):
+    """Time candidate tunings on the ranges [los[i], his[i]) (count only), or
+    on `los` given as an INTERVAL_DTYPE array (his None), whose bitmap flags
+    and word offsets are kept; returns (tuning dict, kernel ms of the winner)."""
+    if his is None:
+        iv = np.ascontiguousarray(los, dtype=INTERVAL_DTYPE)
+    else:
+        los = np.atleast_1d(np.asarray(los, dtype=np.uint64))
+        his = np.atleast_1d(np.asarray(his, dtype=np.uint64))
+        iv = np.zeros(len(los), dtype=INTERVAL_DTYPE)
+        iv["lo"], iv["hi"] = los, his
     t = sieve_tuning()
     ms = ctypes.c_double(0)
     flags = (SIEVE_TUNE_APPLY if apply else 0) | (SIEVE_TUNE_FORCE if force else 0)

@@ -45,6 +45,29 @@ def test_marks_match_enumeration(lo, hi):
     assert w["marks_wheel30"] == _enumerated_marks(lo, hi, 7)
 
 
+def _enumerated_issued(lo, hi):
+    """The atomics the kernels issue: odd m in [lo, hi), m = p*k with
+    p >= 37, p^2 <= m and k prime to 30, once per such prime."""
+    n = 0
+    for p in _primes_upto(max(math.isqrt(max(hi - 1, 0)), 2)).tolist():
+        if p < 37 or p * p > hi - 1:
+            continue
+        for m in range(max(p * p, lo), hi):
+            if m % p == 0 and math.gcd(m // p, 30) == 1:
+                n += 1
+    return n
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 2000), (2, 10007), (1369, 1370), (40000, 47321), (123457, 130000)])
+def test_issued_marks_match_enumeration(lo, hi):
+    primes = _primes_upto(1000)
+    roof = bench.lds_roofline(primes, [(lo, hi)], 1.0)
+    w = roof["work_per_launch"]
+    assert w["issued_marks"] == _enumerated_issued(lo, hi)
+    assert w["issued_lds_lane_ops"] == w["issued_marks"] + bench.ISSUED_OPS_PER_WORD * w["words"]
+    assert w["issued_marks"] <= w["marks"]
+
+
 def test_roofline_sums_over_intervals():
     primes = _primes_upto(2000)
     ivs = [(10**6, 10**6 + 3001), (5, 5), (2, 99991), (3 * 10**6, 3 * 10**6 + 64)]
