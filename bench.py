@@ -583,6 +583,8 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0, help="tuning: threads per workgroup")
     ap.add_argument("--bucket-limit", type=int, default=0,
                     help="tuning: primes from here on go through hit buckets (0 automatic, 4294967295 never)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the LDS and VALU microbenchmarks (sieve_measure_peaks) and print them")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -607,6 +609,12 @@ def main():
         return
 
     import paper_1205_4883_amd as sv
+
+    if args.peaks:
+        s = sv.Sieve(0)
+        print(json.dumps({"peaks": sv.sieve_measure_peaks(s.ctx)}), flush=True)
+        s.close()
+        return
 
     if args.workload == "mr-2e24":
         r = run_mr(sv, torch, args.steps, args.warmup)

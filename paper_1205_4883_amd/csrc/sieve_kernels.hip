@@ -1205,8 +1205,18 @@ uint32_t batch_blocks_per_cu(uint32_t seg_words, uint32_t threads)
 
 void range_chunks(uint32_t n_segments, uint32_t grid, uint32_t *chunk, uint32_t *n_chunks)
 {
-    // the last 2 * grid segments go singly; the rest in runs that give each
-    // workgroup about three runs
+    // Beyond two rounds, the last 2 * grid segments go singly; the rest in
+    // runs that give each workgroup about three runs.
+    if (n_segments > grid && n_segments <= 2 * grid) {
+        // Two rounds at most: pairs of consecutive segments, one pair per
+        // workgroup, so that the second segment of each pair continues its
+        // carried sparse primes and takes the reversed dense order
+        // (bitmap of [2, 1e9), 1018 segments on 512 workgroups: 0.0817 ->
+        // 0.0735 ms).
+        *chunk = 2;
+        *n_chunks = n_segments / 2;
+        return;
+    }
     const uint32_t tail = n_segments < 2 * grid ? n_segments : 2 * grid;
     const uint32_t bulk = n_segments - tail;
     uint32_t c = grid ? bulk / (3 * grid) : 0;
