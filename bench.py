@@ -454,7 +454,9 @@ def run_serve(sv, seconds, modes=("batched", "plain"), rate=2000.0):
                      "max_batch": st["max_batch_seen"], "max_inflight": st["max_inflight"],
                      "single_launches": st["single_launches"], "deferred": st["deferred"],
                      "graph_captures": st["graph_captures"], "device_pool_bytes": st["device_pool_bytes"],
-                     "peak_admitted_bytes": st["peak_admitted_bytes"]}
+                     "peak_admitted_bytes": st["peak_admitted_bytes"],
+                     "max_launch_call_ms": st["max_launch_call_ns"] * 1e-6,
+                     "slow_launch_calls": st["slow_launch_calls"]}
         pis[mode], lats[mode] = pi, lat
     if len(pis) == 2:
         assert np.array_equal(pis["batched"], pis["plain"]), "served results differ by mode"

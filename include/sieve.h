@@ -321,6 +321,8 @@ typedef struct sieve_peaks {
     double lds_or_scatter_lane_ops_per_s; /* ds_or_b32 at random words of 64 KiB */
     double lds_read_lane_ops_per_s;       /* ds_read_b32, conflict-free */
     double lds_write_b64_bytes_per_s;     /* ds_write_b64, conflict-free, in bytes */
+    double lds_or_wave_instr_per_s;       /* conflict-free ds_or_b32 wavefront instructions */
+    double lds_or_half_lanes_wave_instr_per_s; /* the same with half the lanes masked off */
     double valu_wave_instr_per_s;         /* int32 add/xor wavefront instructions */
     double valu_wave_instr_per_clk_cu;    /* the same per CU per shader clock */
     double lds_or_clock_hz;               /* shader clock during the ds_or_b32 kernel */
@@ -399,6 +401,9 @@ typedef struct sieve_server_stats {
     uint64_t device_pool_bytes; /* size of the device bitmap pool */
     uint64_t graph_captures;    /* batch graphs captured after creation (0 unless a
                                    batch outgrew the buffers sized at creation) */
+    uint64_t max_launch_call_ns; /* longest time the dispatcher spent queueing one
+                                    batch or launch (host side) */
+    uint64_t slow_launch_calls; /* such calls that took over 1 ms */
 } sieve_server_stats;
 
 /* Start a server on HIP device hip_device (cfg NULL = defaults).  Builds the

@@ -44,7 +44,8 @@ __device__ __forceinline__ void sample_end(ClockSample *cs)
 //         words, so the banks of a half-wavefront are independent and
 //         uniform;
 // mode 3: ds_read_b32, same addresses as mode 0 (summed into a register);
-// mode 4: ds_write_b64, lane l of each half-wavefront on banks 2l, 2l + 1.
+// mode 4: ds_write_b64, lane l of each half-wavefront on banks 2l, 2l + 1;
+// mode 5: mode 0 with only the even lanes active (half the lanes masked off).
 template <int kMode>
 __global__ void __launch_bounds__(kThreads) lds_peak_kernel(uint32_t passes, ClockSample *cs, uint32_t *sink)
 {
@@ -70,7 +71,8 @@ __global__ void __launch_bounds__(kThreads) lds_peak_kernel(uint32_t passes, Clo
         rnd[k] = h & 16383u;
     }
     uint32_t acc = 0;
-    for (uint32_t p = 0; p < passes; ++p) {
+    const bool active = kMode != 5 || (lane & 1) == 0;
+    for (uint32_t p = 0; active && p < passes; ++p) {
 #pragma unroll
         for (uint32_t k = 0; k < kLdsUnroll; ++k) {
             if (kMode == 2)
@@ -224,6 +226,13 @@ int sieve_measure_peaks(sieve_ctx *c, sieve_peaks *out)
         if (st)
             break;
         r.lds_write_b64_bytes_per_s = 8 * lanes * lds_passes * kLdsUnroll / (ms * 1e-3);
+        ms = run([&] {
+            hipLaunchKernelGGL(lds_peak_kernel<5>, dim3(grid), dim3(kThreads), 0, c->stream, lds_passes, d_cs, d_sink);
+        });
+        if (st)
+            break;
+        r.lds_or_half_lanes_wave_instr_per_s = (lanes / 64) * lds_passes * kLdsUnroll / (ms * 1e-3);
+        r.lds_or_wave_instr_per_s = r.lds_or_lane_ops_per_s / 64;
         ms = run([&] {
             hipLaunchKernelGGL(valu_peak_kernel, dim3(grid), dim3(kThreads), 0, c->stream, valu_passes, d_cs, d_sink);
         });

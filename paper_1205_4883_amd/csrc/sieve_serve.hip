@@ -14,6 +14,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <deque>
 #include <iterator>
 #include <map>
@@ -80,6 +82,13 @@ struct sieve_server {
     sv::Buddy arena;
     uint64_t items_cap = 0;        // work items a batch may hold
     uint64_t captures_at_create = 0;
+    // Steps of the launch call in progress (dispatcher thread only): with
+    // SIEVE_SERVE_LOG_SLOW set in the environment, a call over 1 ms prints
+    // how long each of its steps took.
+    bool log_slow = false;
+    int n_steps = 0;
+    const char *step_name[8] = {};
+    uint64_t step_ns[8] = {};
 
     std::mutex m;
     std::condition_variable cv_work;  // dispatcher: new submissions or stop
@@ -96,6 +105,14 @@ struct sieve_server {
 };
 
 namespace {
+
+void step(sieve_server *s, const char *name)
+{
+    if (s->n_steps < 8) {
+        s->step_name[s->n_steps] = name;
+        s->step_ns[s->n_steps++] = now_ns();
+    }
+}
 
 constexpr uint32_t kDefaultLanes = 3;
 constexpr uint32_t kDefaultMaxBatch = 1024;
@@ -193,11 +210,14 @@ int launch_single_lane(sieve_server *s, Lane &lane)
     *lane.h_pub = kUnpublished;
     r->t_launch = now_ns();
     const int st = sv::range_async(c, r->lo, r->hi, d, lane.d_pub, lane.stream);
+    step(s, "range launch");
     if (st != SIEVE_OK)
         return st;
     if (d)
         SV_HIP_TRY(c, hipMemcpyAsync(r->host, d, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
+    step(s, "bitmap copy");
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
+    step(s, "event");
     lane.single = true;
     lane.busy = true;
     return SIEVE_OK;
@@ -219,16 +239,20 @@ int launch_batch_lane(sieve_server *s, Lane &lane)
     }
     if (int st = sv::engine_stage(c, lane.eng, lane.iv.data(), n, s->d_pool, s->pool.size() / 4))
         return st;
+    step(s, "batch stage");
     const uint64_t t = now_ns();
     for (Request *r : lane.reqs)
         r->t_launch = t;
     if (int st = sv::engine_launch(c, lane.eng, s->d_pool, lane.stream, false))
         return st;
+    step(s, "batch launch");
     for (const Request *r : lane.reqs)
         if (wants_words(r))
             SV_HIP_TRY(c, hipMemcpyAsync(r->host, dev_words(s, r), r->n_words * 4, hipMemcpyDeviceToHost,
                                          lane.stream));
+    step(s, "bitmap copies");
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
+    step(s, "event");
     lane.single = false;
     lane.busy = true;
     return SIEVE_OK;
@@ -323,13 +347,27 @@ void dispatcher(sieve_server *s)
                 lane.reqs.clear();
                 s->cv_done.notify_all();
             } else {
+                const uint64_t t_call = now_ns();
+                s->n_steps = 0;
+                step(s, "start");
                 st = sv::kNotAsync;
                 if (lane.reqs.size() == 1)
                     st = launch_single_lane(s, lane);
                 const bool single = st == SIEVE_OK;
                 if (st == sv::kNotAsync)
                     st = launch_batch_lane(s, lane);
+                const uint64_t call_ns = now_ns() - t_call;
                 std::lock_guard<std::mutex> g(s->m);
+                s->stats.max_launch_call_ns = std::max(s->stats.max_launch_call_ns, call_ns);
+                s->stats.slow_launch_calls += call_ns > 1000000 ? 1 : 0;
+                if (s->log_slow && call_ns > 1000000) {
+                    std::fprintf(stderr, "sieve server: launch call of %zu request(s) took %.3f ms:", lane.reqs.size(),
+                                 call_ns * 1e-6);
+                    for (int k = 1; k < s->n_steps; ++k)
+                        std::fprintf(stderr, " %s %.3f", s->step_name[k],
+                                     (s->step_ns[k] - s->step_ns[k - 1]) * 1e-6);
+                    std::fprintf(stderr, "\n");
+                }
                 ++s->stats.batches;
                 s->stats.single_launches += single ? 1 : 0;
                 s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, lane.reqs.size());
@@ -415,6 +453,7 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
         return SIEVE_EINVAL;
     }
     s->items_cap = std::max<uint64_t>(kMinItemsCap, 16ull * s->cfg.max_batch);
+    s->log_slow = std::getenv("SIEVE_SERVE_LOG_SLOW") != nullptr;
     // The HBM budget is charged with the server's fixed device memory first
     // (the context and each lane's batch buffers); the rest is the bitmap
     // pool, allocated here, so that admitted requests never hold more.
@@ -443,6 +482,15 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
         if (arena == 0 || hipHostMalloc(&s->h_arena, arena, hipHostMallocDefault) != hipSuccess) {
             s->h_arena = nullptr;
             st = SIEVE_ENOMEM;
+        }
+        // Copy device memory over the whole arena once, so that the first
+        // bitmap copied into each of its blocks while serving does not pay
+        // for first-use set-up of its pages.
+        const uint64_t pool = s->pool.size();
+        for (uint64_t off = 0; st == SIEVE_OK && off < arena; off += pool) {
+            const uint64_t n = std::min<uint64_t>(pool, arena - off);
+            if (hipMemcpy(static_cast<char *>(s->h_arena) + off, s->d_pool, n, hipMemcpyDeviceToHost) != hipSuccess)
+                st = SIEVE_EDEVICE;
         }
     }
     s->lanes.resize(s->cfg.lanes);
@@ -488,6 +536,30 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
                 st = SIEVE_EDEVICE;
             lane.eng.pending = false;
         }
+    }
+    // Warm every lane before serving: one large bitmap copy to the host on
+    // its stream, and one launch of each plain range kernel the loop may use
+    // (every segment capacity, counting and writing).  First uses cost
+    // milliseconds that would otherwise land on the first requests.
+    for (Lane &lane : s->lanes) {
+        if (st != SIEVE_OK)
+            break;
+        const uint64_t copy = std::min<uint64_t>({64ull << 20, s->pool.size(), s->arena.size()});
+        if (hipMemcpyAsync(s->h_arena, s->d_pool, copy, hipMemcpyDeviceToHost, lane.stream) != hipSuccess)
+            st = SIEVE_EDEVICE;
+        const uint64_t words_cap = s->pool.size() / 4;
+        for (uint64_t n_words : {10000ull, 800000ull, 3000000ull, 8000000ull, 40000000ull}) {
+            for (int bm = 0; bm < 2 && st == SIEVE_OK; ++bm) {
+                if (bm && n_words > words_cap)
+                    continue;
+                const int r = sv::range_async(s->ctx, 0, 64 * n_words, bm ? s->d_pool : nullptr, lane.d_pub,
+                                              lane.stream);
+                if (r != SIEVE_OK && r != sv::kNotAsync)
+                    st = r;
+            }
+        }
+        if (st == SIEVE_OK && hipStreamSynchronize(lane.stream) != hipSuccess)
+            st = SIEVE_EDEVICE;
     }
     if (st != SIEVE_OK) {
         s->stop = true;

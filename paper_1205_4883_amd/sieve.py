@@ -63,6 +63,8 @@ class sieve_peaks(ctypes.Structure):
                 ("lds_write_lane_ops_per_s", ctypes.c_double),
                 ("lds_or_scatter_lane_ops_per_s", ctypes.c_double),
                 ("lds_read_lane_ops_per_s", ctypes.c_double), ("lds_write_b64_bytes_per_s", ctypes.c_double),
+                ("lds_or_wave_instr_per_s", ctypes.c_double),
+                ("lds_or_half_lanes_wave_instr_per_s", ctypes.c_double),
                 ("valu_wave_instr_per_s", ctypes.c_double), ("valu_wave_instr_per_clk_cu", ctypes.c_double),
                 ("lds_or_clock_hz", ctypes.c_double), ("valu_clock_hz", ctypes.c_double),
                 ("n_cu", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
@@ -89,7 +91,8 @@ class sieve_server_stats(ctypes.Structure):
                 ("max_batch_seen", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                 ("peak_admitted_bytes", ctypes.c_uint64), ("peak_host_bytes", ctypes.c_uint64),
-                ("device_pool_bytes", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64)]
+                ("device_pool_bytes", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64),
+                ("max_launch_call_ns", ctypes.c_uint64), ("slow_launch_calls", ctypes.c_uint64)]
 
 
 INTERVAL_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8"), ("word_offset", "<u8"),

@@ -186,12 +186,13 @@ def test_additivity_on_gpu(gpu):
         assert gpu.count(a, c) == gpu.count(a, b) + gpu.count(b, c)
 
 
-def test_properties_of_a_large_range_near_the_top(gpu):
-    # at a size the oracle is not run on: [1e15 - 2^33, 1e15) (2^32 odd
-    # integers, 512 MiB of bitmap).  The words of [a, b) and [b, c) (b at a
-    # multiple of 64 from a) concatenate to those of [a, c); the count equals
-    # the bitmap's popcount; sampled set bits are prime and sampled clear
-    # bits composite by the GPU's own Miller-Rabin.
+def test_properties_of_a_large_range_near_the_top(gpu, oracle_mod):
+    # at a size the oracle is not run on whole: [1e15 - 2^33, 1e15) (2^32
+    # odd integers, 512 MiB of bitmap).  The words of [a, b) and [b, c) (b at
+    # a multiple of 64 from a) concatenate to those of [a, c); the count
+    # equals the bitmap's popcount; twelve sampled 2048-word windows equal
+    # the oracle's bitmap of the same integers; and sampled set bits are
+    # prime and sampled clear bits composite by Miller-Rabin.
     print("case large-range properties below 1e15", flush=True)
     torch = gpu.torch
     a, c = 10**15 - 2**33, 10**15
@@ -211,6 +212,12 @@ def test_properties_of_a_large_range_near_the_top(gpu):
     assert total == pi_ac  # no 2 in range
     rng = random.Random(17)
     words = w_ac.cpu().numpy().view(np.uint32)
+    starts = [0, words.size - 2048] + [rng.randrange(0, words.size - 2048) for _ in range(10)]
+    for w0 in starts:
+        lo_w = a + 64 * w0
+        hi_w = min(c, lo_w + 64 * 2048)
+        ref, _ = oracle_mod.bitmap(lo_w, hi_w)
+        assert np.array_equal(words[w0:w0 + ref.size], ref), (lo_w, hi_w)
     ns, want = [], []
     base = (a & ~1) + 1
     for _ in range(4000):
@@ -490,7 +497,9 @@ def test_bucketed_ranges(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, limit, depth
         gpu.tuning(seg_bits=0, bucket_limit=0, bucket_depth=0)
 
 
-def test_buckets_off_and_on_agree(gpu, sv_mod):
+def test_buckets_off_and_on_agree(gpu, sv_mod, oracle_mod):
+    # the same range with the large primes scanned per segment and through
+    # hit buckets: both equal the oracle
     lo, hi = 10**14, 10**14 + 6 * 10**7
     gpu.tuning(bucket_limit=0xFFFFFFFF)
     try:
@@ -506,6 +515,8 @@ def test_buckets_off_and_on_agree(gpu, sv_mod):
     finally:
         gpu.tuning(bucket_limit=0)
     assert p0 == p1 and np.array_equal(a, w1.cpu().numpy())
+    ref, ref_pi = oracle_mod.bitmap(lo, hi)
+    assert p0 == ref_pi and np.array_equal(a.view(np.uint32), ref)
 
 
 # -- kernel timing switch and the count call's early return ---------------------
