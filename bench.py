@@ -22,7 +22,10 @@ figure, 256 CUs x 32 banks x 2.4 GHz, beside it).  The work is one 32-bit LDS
 atomic per crossed-off odd multiple m of every base prime 37 <= p <=
 sqrt(hi-1), max(p^2, lo) <= m < hi (the kernels strike 3..31 with periodic
 pre-sieve tables), plus one LDS write and one read per bitmap word;
-frac_wheel30 prices the larger wheel-30 work (marks from p = 7).  Its `units`
+issued_frac prices the atomics the kernels actually issue (multipliers prime
+to 30) plus their per-word LDS accesses.  The wheel-30 work (marks from p = 7,
+which a build pre-sieving only 3 and 5 would do) is in work_per_launch for
+comparison; it is not priced, since this build strikes 7..31 with tables.  Its `units`
 object gives each unit's use from the committed rocprofv3 counters of the
 same kernel source (VALU issue against the measured VALU peak, LDS busy and
 bank-conflict cycles), and `bound` names the busier one.  The cpu_baseline
@@ -149,7 +152,8 @@ def algorithmic_lds_ops(primes, lo, hi, pmin=FIRST_MARKED_PRIME):
 def lds_roofline(primes, ranges, seconds):
     """LDS roofline object for one launch that sieves `ranges` in `seconds`:
     frac prices this build's own work (marks of primes from 37 up), and
-    frac_wheel30 the wheel-30 work (marks from 7 up) for comparison."""
+    issued_frac the atomics and per-word accesses the kernels issue; the
+    wheel-30 work (marks from 7 up) is reported beside them, not priced."""
     import math
 
     import numpy as np
@@ -175,7 +179,6 @@ def lds_roofline(primes, ranges, seconds):
     return {
         "bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_LANE_OPS / 1e9,
         "unit": "Glane-op/s", "frac": achieved / LDS_PEAK_LANE_OPS,
-        "frac_wheel30": lane_ops30 / seconds / LDS_PEAK_LANE_OPS,
         "issued_frac": issued_ops / seconds / LDS_PEAK_LANE_OPS,
         "work_per_launch": {"marks": marks, "lds_lane_ops": lane_ops, "words": words,
                             "first_marked_prime": FIRST_MARKED_PRIME,
@@ -269,7 +272,6 @@ def measured_roofline(primes, ranges, seconds, peaks, counters, workload_key, ke
         roof["peak_planning"] = roof["peak"]
         roof["peak"] = measured / 1e9
         roof["frac"] = roof["achieved"] * 1e9 / measured
-        roof["frac_wheel30"] = roof["frac_wheel30"] * LDS_PEAK_LANE_OPS / measured
         roof["issued_frac"] = roof["issued_frac"] * LDS_PEAK_LANE_OPS / measured
         roof["peak_source"] = "measured: conflict-free ds_or_b32 on every CU (sieve_measure_peaks)"
     bound, units = unit_use(counters, peaks, N_CU, seconds * 1e3)
