@@ -343,10 +343,13 @@ SIEVE_API int sieve_measure_peaks(sieve_ctx *ctx, sieve_peaks *out);
  * room in two budgets that are real memory: a device pool of the HBM budget
  * (less the server's fixed device memory, allocated once at creation) and a
  * pinned host arena for the returned bitmaps.  Admitted requests are packed
- * into batches (the sieve_batch work queue) on up to `lanes` streams at
- * once, so requests that arrive while others run are batched and overlap on
- * the device (the paper's overlap of communication and computation,
- * Section 2.2).  Results are identical to sieving each range alone.
+ * into batches on up to `lanes` streams at once, so requests that arrive
+ * while others run are batched and overlap on the device (the paper's
+ * overlap of communication and computation, Section 2.2).  A batch of up to
+ * 8 requests goes as plain range launches, one per request, on its lane's
+ * stream; a larger one (or one with an empty or bucketed range) as one
+ * launch of the sieve_batch work queue.  Results are identical to sieving
+ * each range alone.
  * ---------------------------------------------------------------------- */
 typedef struct sieve_server sieve_server;
 
@@ -365,7 +368,9 @@ typedef struct sieve_server_config {
                                   256 MiB hit-bucket pool), and the rest as the
                                   pool the admitted bitmaps live in */
     uint64_t host_arena_bytes; /* pinned host memory for returned bitmaps,
-                                  held until released [2 GiB] */
+                                  held until released [2 GiB]; mapped into
+                                  the device, where batched mode's copy
+                                  kernels write them */
     uint32_t mode;             /* SIEVE_SERVE_BATCHED or SIEVE_SERVE_PLAIN */
     uint32_t pad;
 } sieve_server_config;
@@ -392,7 +397,8 @@ typedef struct sieve_server_stats {
     uint64_t submitted;
     uint64_t completed;
     uint64_t batches;           /* batches (or plain launches) issued */
-    uint64_t single_launches;   /* batches of one served by the plain range launch */
+    uint64_t single_launches;   /* batches of up to 8 requests served by plain
+                                   range launches, one per request */
     uint64_t max_batch_seen;    /* most requests in one batch */
     uint64_t max_inflight;      /* most batches on the device at once */
     uint64_t deferred;          /* admissions that had to wait for budget */

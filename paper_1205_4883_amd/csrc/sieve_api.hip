@@ -168,7 +168,17 @@ int make_plan(uint64_t lo, uint64_t hi, const sieve_tuning *tu, uint32_t n_cu, u
 // launch is enqueued.
 int take_slot(sieve_ctx *c, hipStream_t s, uint32_t **words)
 {
-    const int i = c->next_slot;
+    // The first slot in turn that is free; only when every slot still has a
+    // launch in flight (launches on several streams, one of them long) does
+    // the call wait, for the oldest.
+    int i = c->next_slot;
+    for (int k = 0; k < sieve_ctx::kSlots; ++k) {
+        const int j = (c->next_slot + k) % sieve_ctx::kSlots;
+        if (!c->slot_used[j] || hipEventQuery(c->slot_done[j]) != hipErrorNotReady) {
+            i = j;
+            break;
+        }
+    }
     c->next_slot = (i + 1) % sieve_ctx::kSlots;
     if (c->slot_used[i])
         HIP_TRY(c, hipEventSynchronize(c->slot_done[i]));
@@ -575,6 +585,13 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
     return SIEVE_OK;
 }
 
+bool range_async_ok(const sieve_ctx *c, uint64_t lo, uint64_t hi)
+{
+    sieve_plan_info pl{};
+    return make_plan(lo, hi, &c->tuning, c->n_cu, c->lds_max, &pl) == SIEVE_OK && pl.nbits != 0 &&
+           !pl.bucket_limit && pl.n_segments <= 0xffffffffull;
+}
+
 int range_async(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, unsigned long long *d_pub,
                 hipStream_t s)
 {
@@ -618,12 +635,18 @@ int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes)
     if (b.p)
         HIP_TRY(c, hipHostFree(b.p));
     b.p = nullptr;
+    b.d = nullptr;
     b.bytes = 0;
-    hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess)
+        e = hipHostGetDevicePointer(&b.d, b.p, 0);
     if (e != hipSuccess) {
         c->last_hip = e;
+        if (b.p)
+            (void)hipHostFree(b.p);
         b.p = nullptr;
-        return SIEVE_ENOMEM;
+        b.d = nullptr;
+        return e == hipErrorOutOfMemory ? SIEVE_ENOMEM : SIEVE_EDEVICE;
     }
     b.bytes = want;
     return SIEVE_OK;
@@ -650,15 +673,12 @@ int capture_batch_graph(sieve_ctx *c, BatchEngine &eng, const GraphKey &k)
     drop_graph(eng, v);
     hipStream_t cs = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = sv::launch_batch(static_cast<sv::BatchHeader *>(const_cast<void *>(k.blob)),
+    hipError_t e = sv::launch_batch(k.h_blob, static_cast<sv::BatchHeader *>(const_cast<void *>(k.blob)),
                                     k.max_intervals, static_cast<const uint32_t *>(k.primes),
                                     static_cast<const double *>(k.inv), k.words,
                                     static_cast<uint32_t *>(const_cast<void *>(k.item_counts)),
                                     static_cast<unsigned long long *>(const_cast<void *>(k.counts)),
                                     k.seg_words, k.threads, k.blocks, k.small, cs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(const_cast<void *>(k.h_counts), k.counts, k.counts_bytes,
-                           hipMemcpyDeviceToHost, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess)
@@ -693,9 +713,9 @@ uint64_t blob_items_offset(uint32_t n)
     const uint64_t iv_bytes = static_cast<uint64_t>(n) * sizeof(sv::BatchInterval);
     return kBlobIntervalOff + (iv_bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
 }
-uint64_t blob_bytes(uint32_t n, uint64_t items)
+uint64_t blob_bytes(uint32_t n, uint64_t items)  // whole 16-byte chunks, as the stage kernel copies
 {
-    return blob_items_offset(n) + std::max<uint64_t>(1, items) * sizeof(uint32_t);
+    return (blob_items_offset(n) + std::max<uint64_t>(1, items) * sizeof(uint32_t) + 15) / 16 * 16;
 }
 }  // namespace
 
@@ -706,11 +726,9 @@ int engine_reserve(sieve_ctx *c, BatchEngine &e, uint32_t n, uint64_t items)
         return st;
     if (int st = grow(c, e.blob, bytes))
         return st;
-    if (int st = grow(c, e.counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long)))
-        return st;
     if (int st = grow(c, e.item_counts, std::max<uint64_t>(1, items) * sizeof(uint32_t)))
         return st;
-    return grow_host(c, e.s_counts, e.counts.bytes);
+    return grow_host(c, e.s_counts, std::max<uint64_t>(1, n) * sizeof(unsigned long long));
 }
 
 void engine_free(BatchEngine &e)
@@ -719,7 +737,7 @@ void engine_free(BatchEngine &e)
         (void)hipEventSynchronize(e.done);
     drop_graph(e, 0);
     drop_graph(e, 1);
-    for (DevBuf *b : {&e.blob, &e.counts, &e.item_counts})
+    for (DevBuf *b : {&e.blob, &e.item_counts})
         if (b->p)
             (void)hipFree(b->p);
     for (HostBuf *b : {&e.s_blob, &e.s_counts})
@@ -740,8 +758,7 @@ uint32_t batch_seg_words(const sieve_ctx *c)
 
 uint64_t engine_device_bytes(uint32_t n, uint64_t items)
 {
-    return blob_bytes(n, items) + std::max<uint64_t>(1, n) * sizeof(unsigned long long) +
-           std::max<uint64_t>(1, items) * sizeof(uint32_t);
+    return blob_bytes(n, items) + std::max<uint64_t>(1, items) * sizeof(uint32_t);
 }
 
 int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_t n, uint32_t *d_words,
@@ -780,9 +797,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
             return SIEVE_EINVAL;
     if (items > 0xffffffffull)
         return SIEVE_ERANGE;
-    const uint64_t dev_bytes = n * sizeof(sv::BatchInterval) + 2 * items * sizeof(uint32_t) +
-                               n * sizeof(unsigned long long) + kBlobIntervalOff;
-    if (dev_bytes > c->hbm_budget)
+    if (engine_device_bytes(n, items) > c->hbm_budget)
         return SIEVE_ENOMEM;
 
     HIP_TRY(c, hipSetDevice(c->device));
@@ -844,7 +859,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     h_hdr->n_intervals = n;
     h_hdr->n_items = static_cast<uint32_t>(items);
     h_hdr->seg_words = sw;
-    h_hdr->pad = 0;
+    h_hdr->blob_chunks = static_cast<uint32_t>(bytes / 16);
     h_hdr->iv_off = kBlobIntervalOff;
     h_hdr->item_off = blob_items_offset(n);
     e.blob_used = bytes;
@@ -863,18 +878,17 @@ int engine_graph(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, bool small)
     if (c->tuning.wg_per_cu)
         per_cu = std::min(per_cu, c->tuning.wg_per_cu);
     GraphKey k{};
+    k.h_blob = e.s_blob.d;
     k.blob = e.blob.p;
-    k.counts = e.counts.p;
+    k.counts = e.s_counts.d;
     k.item_counts = e.item_counts.p;
-    k.h_counts = e.s_counts.p;
     k.primes = c->d_primes + sv::kPresievePrimes;
     k.inv = c->d_inv + sv::kPresievePrimes;
     k.words = d_words;
     k.seg_words = e.seg_words;
     k.threads = e.threads;
     k.blocks = per_cu * c->n_cu;
-    k.max_intervals = static_cast<uint32_t>(e.counts.bytes / sizeof(unsigned long long));
-    k.counts_bytes = e.counts.bytes;
+    k.max_intervals = static_cast<uint32_t>(e.s_counts.bytes / sizeof(unsigned long long));
     k.small = small;
     const int v = small ? 1 : 0;
     if (!e.exec[v] || !(e.key[v] == k))
@@ -889,7 +903,6 @@ int engine_launch(sieve_ctx *c, BatchEngine &e, uint32_t *d_words, hipStream_t s
         return st;
     if (int st = engine_graph(c, e, d_words, e.small))
         return st;
-    HIP_TRY(c, hipMemcpyAsync(e.blob.p, e.s_blob.p, e.blob_used, hipMemcpyHostToDevice, s));
     if (timed) {
         c->ev_valid = false;
         HIP_TRY(c, hipEventRecord(c->ev_start, s));

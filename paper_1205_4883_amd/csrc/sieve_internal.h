@@ -98,7 +98,7 @@ struct BatchHeader {
     uint32_t n_intervals;
     uint32_t n_items;
     uint32_t seg_words;  // words per work item (segment)
-    uint32_t pad;
+    uint32_t blob_chunks;  // 16-byte chunks of the whole blob (what the stage kernel copies)
     uint64_t iv_off;
     uint64_t item_off;
 };
@@ -132,20 +132,28 @@ hipError_t launch_bucket_fill(const uint32_t *primes, const double *inv, uint32_
 // inv[i] = 1.0 / primes[i] for i < n.
 hipError_t launch_reciprocals(const uint32_t *d_primes, uint32_t n, double *d_inv, hipStream_t s);
 
+// dst[0, n_words) = src[0, n_words) by a kernel on s; both 16-byte aligned,
+// dst may be host memory mapped into the device.
+hipError_t launch_copy_words(const uint32_t *src, uint32_t *dst, uint64_t n_words, hipStream_t s);
+
 // Compaction of a bitmap (1 = prime) into the ascending list of the integers
 // its set bits stand for.  d_tmp needs compact_tmp_words(n_words) words.
 uint64_t compact_tmp_words(uint64_t n_words);
 hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t first_odd,
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s);
 
-// Reset kernel (the work queues), the persistent batch kernel (each work
-// item's count into item_counts[item]) and the reduction kernel (counts[k] =
-// the sum over interval k's items); all three read their sizes and the table
-// offsets from the blob's header.  max_intervals sizes the reduction grid.
-// small: every marking prime of the batch is below 2^24 (24-bit products).
-hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
+// Stage kernel (copies the blob from h_blob, the device-visible address of
+// its pinned host staging, into d_blob and clears the work queues), the
+// persistent batch kernel (each work item's count into item_counts[item])
+// and the reduction kernel (counts[k] = the sum over interval k's items;
+// counts may be mapped host memory).  All read their sizes and the table
+// offsets from the blob's header, so one captured graph serves every batch
+// that fits its buffers.  max_intervals sizes the reduction grid.  small:
+// every marking prime of the batch is below 2^24 (24-bit products).
+constexpr uint32_t kStageBlocks = 64;
+hipError_t launch_batch(const void *h_blob, BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
                         const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
-                        unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
+                        unsigned long long *counts, uint32_t seg_words, uint32_t block_threads,
                         uint32_t n_blocks, bool small, hipStream_t s);
 
 // The segment kernels are built for a few static LDS sizes: the smallest

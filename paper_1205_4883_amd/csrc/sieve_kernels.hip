@@ -780,11 +780,18 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 
 // Zero a batch's work queues (a kernel, not a memset, so that it can sit in a
 // captured graph).
-__global__ void __launch_bounds__(64) batch_reset_kernel(BatchHeader *hdr)
+// Copies a batch's blob (header, work queues, interval table, work list)
+// from the pinned host staging into device memory, with the work-queue
+// counters cleared, so that a batch launch is kernels only: no upload on a
+// copy engine.  The length is the header's blob_chunks, read once per
+// wavefront from the host copy.
+__global__ void __launch_bounds__(256) batch_stage_kernel(const uint4 *src, uint4 *dst)
 {
-    uint32_t *counters = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hdr) + kBlobCounterOff);
-    if (threadIdx.x < kQueues)
-        counters[threadIdx.x * kLineWords] = 0;
+    const uint32_t n = __builtin_amdgcn_readfirstlane(reinterpret_cast<const BatchHeader *>(src)->blob_chunks);
+    constexpr uint32_t c0 = kBlobCounterOff / 16, c1 = kBlobIntervalOff / 16;
+    static_assert(kBlobCounterOff % 16 == 0 && kBlobIntervalOff % 16 == 0, "blob regions are 16-byte chunks");
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dst[i] = (i >= c0 && i < c1) ? make_uint4(0, 0, 0, 0) : src[i];
 }
 
 // counts[k] = the sum of item_counts over interval k's items, one wavefront
@@ -808,6 +815,33 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchHeader *hd
         if (lane == 0)
             counts[k] = c;
     }
+}
+
+// dst[0, n_words) = src[0, n_words), 16 bytes per thread and step, four
+// loads in flight per thread (both 16-byte aligned).  The server returns
+// bitmaps with it into its pinned host arena, mapped into the device, so
+// that a copy runs on the lane's compute queue in stream order instead of on
+// a copy engine.
+__global__ void __launch_bounds__(256) copy_words_kernel(const uint4 *src, uint4 *dst, uint64_t n_words)
+{
+    constexpr int kU = 4;
+    const uint64_t n16 = n_words / 4;
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    uint64_t i = t;
+    for (; i + (kU - 1) * stride < n16; i += kU * stride) {
+        uint4 v[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k)
+            v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < kU; ++k)
+            dst[i + k * stride] = v[k];
+    }
+    for (; i < n16; i += stride)
+        dst[i] = src[i];
+    if (t < n_words % 4)
+        reinterpret_cast<uint32_t *>(dst)[4 * n16 + t] = reinterpret_cast<const uint32_t *>(src)[4 * n16 + t];
 }
 
 // Odd integers below 2^16 in one workgroup: bit i of bits[] is 2i + 1,
@@ -1254,6 +1288,22 @@ uint64_t compact_tmp_words(uint64_t n_words)
     return (n_words + kCompactChunk - 1) / kCompactChunk + 1;
 }
 
+hipError_t launch_copy_words(const uint32_t *src, uint32_t *dst, uint64_t n_words, hipStream_t s)
+{
+    if (n_words == 0)
+        return hipSuccess;
+    // 16 workgroups with four loads in flight per thread already reach the
+    // PCIe rate to host memory (measured 52-56 GB/s for 8-64 MiB, as fast as
+    // a copy-engine copy); more would only hold CU slots (a CU running a
+    // sieve launch's two workgroups has none free) that concurrent sieve
+    // launches need.
+    const uint64_t n16 = (n_words + 3) / 4;
+    const uint32_t blocks = static_cast<uint32_t>(n16 < 16 * 256 ? (n16 + 255) / 256 : 16);
+    hipLaunchKernelGGL(copy_words_kernel, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src),
+                       reinterpret_cast<uint4 *>(dst), n_words);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t first_odd,
                           uint32_t *d_tmp, uint32_t *d_out, uint32_t *d_total, hipStream_t s)
 {
@@ -1268,14 +1318,15 @@ hipError_t launch_compact(const uint32_t *d_words, uint64_t n_words, uint64_t fi
     return hipGetLastError();
 }
 
-hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
+hipError_t launch_batch(const void *h_blob, BatchHeader *d_blob, uint32_t max_intervals, const uint32_t *d_primes,
                         const double *d_inv, uint32_t *d_words, uint32_t *d_item_counts,
-                        unsigned long long *d_counts, uint32_t seg_words, uint32_t block_threads,
+                        unsigned long long *counts, uint32_t seg_words, uint32_t block_threads,
                         uint32_t n_blocks, bool small, hipStream_t s)
 {
     if (n_blocks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, d_blob);
+    hipLaunchKernelGGL(batch_stage_kernel, dim3(kStageBlocks), dim3(256), 0, s, static_cast<const uint4 *>(h_blob),
+                       reinterpret_cast<uint4 *>(d_blob));
     switch (seg_capacity_for(seg_words)) {
     case 512: launch_batch_cap<512>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
     case 2048: launch_batch_cap<2048>(d_blob, d_primes, d_inv, d_words, d_item_counts, seg_words, block_threads, n_blocks, small, s); break;
@@ -1286,7 +1337,7 @@ hipError_t launch_batch(BatchHeader *d_blob, uint32_t max_intervals, const uint3
     }
     const uint32_t waves_blocks = (max_intervals + 3) / 4;  // four wavefronts per block
     const uint32_t rb = waves_blocks == 0 ? 1 : (waves_blocks < 1024 ? waves_blocks : 1024);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(rb), dim3(256), 0, s, d_blob, d_item_counts, d_counts);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(rb), dim3(256), 0, s, d_blob, d_item_counts, counts);
     return hipGetLastError();
 }
 

@@ -25,33 +25,33 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-struct HostBuf {  // pinned host memory
+struct HostBuf {  // pinned, coherent host memory, mapped into the device
     void *p = nullptr;
+    void *d = nullptr;  // its device-visible address
     size_t bytes = 0;
 };
 
 // Everything a captured batch graph bakes in.
 struct GraphKey {
-    const void *blob, *counts, *item_counts, *h_counts, *primes, *inv;
+    const void *h_blob, *blob, *counts, *item_counts, *primes, *inv;
     uint32_t *words;
     uint32_t seg_words, threads, blocks, max_intervals;
-    size_t counts_bytes;
     bool small;  // every marking prime below 2^24
     bool operator==(const GraphKey &o) const
     {
-        return blob == o.blob && counts == o.counts && item_counts == o.item_counts && h_counts == o.h_counts &&
+        return h_blob == o.h_blob && blob == o.blob && counts == o.counts && item_counts == o.item_counts &&
                primes == o.primes && inv == o.inv && words == o.words && seg_words == o.seg_words &&
-               threads == o.threads && blocks == o.blocks && max_intervals == o.max_intervals &&
-               counts_bytes == o.counts_bytes && small == o.small;
+               threads == o.threads && blocks == o.blocks && max_intervals == o.max_intervals && small == o.small;
     }
 };
 
 // One batch in flight: the interval table and work list (pinned staging and
-// device copies), per-item and per-interval counts, the batch header and the
+// device copies), per-item counts, the per-interval counts (written by the
+// device straight into mapped host memory), the batch header and the
 // captured graph that launches it.  A context owns one; the server owns one
 // per lane.
 struct BatchEngine {
-    DevBuf blob, counts, item_counts;  // blob: header, work queues, interval table, work list
+    DevBuf blob, item_counts;  // blob: header, work queues, interval table, work list
     HostBuf s_blob, s_counts;
     uint64_t blob_used = 0;  // bytes of the staged blob
     std::vector<uint32_t> order;  // intervals in queue order
@@ -157,13 +157,17 @@ int run_range(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, uint64_
 constexpr int kNotAsync = 1;
 int range_async(sieve_ctx *c, uint64_t lo, uint64_t hi, uint32_t *d_words, unsigned long long *d_pub,
                 hipStream_t s);
+// Whether range_async would enqueue [lo, hi) (a valid, non-empty range that
+// needs no hit buckets).
+bool range_async_ok(const sieve_ctx *c, uint64_t lo, uint64_t hi);
 int grow(sieve_ctx *c, DevBuf &b, size_t bytes);
 int grow_host(sieve_ctx *c, HostBuf &b, size_t bytes);
 
 // Batch engine.  stage: validate the intervals and build the work list in
 // the engine's pinned staging (waits for the engine's previous launch).
-// launch: upload and launch the batch graph on s (asynchronous); the counts
-// (excluding the even prime 2) land in counts_host() once `done` completes.
+// launch: launch the batch graph on s (asynchronous; its first kernel copies
+// the staging to the device); the counts (excluding the even prime 2) land
+// in counts_host() once `done` completes.
 int engine_init(sieve_ctx *c, BatchEngine &e);
 // Grow the engine's buffers ahead of time for n intervals and `items` work
 // items, so that batches up to that size never re-capture the graph.

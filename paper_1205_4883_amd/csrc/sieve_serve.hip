@@ -59,13 +59,18 @@ struct Lane {
     std::vector<Request *> reqs;
     std::vector<sieve_interval> iv;
     bool busy = false;
-    bool single = false;  // the launch in flight is one plain range launch
-    // pinned and mapped: the count a single launch publishes
+    bool single = false;  // the launches in flight are plain range launches, one per request
+    uint64_t calls = 0;   // launch calls made on this lane (for the slow-call log)
+    uint64_t t_launch = 0;
+    // pinned and mapped: the counts plain launches publish, one word per
+    // request (kMaxPlainBatch)
     volatile unsigned long long *h_pub = nullptr;
     unsigned long long *d_pub = nullptr;
 };
 
 constexpr unsigned long long kUnpublished = ~0ull;
+// Batches of up to this many requests go as plain launches, one per request.
+constexpr size_t kMaxPlainBatch = 8;
 
 }  // namespace
 
@@ -79,6 +84,7 @@ struct sieve_server {
     uint32_t *d_pool = nullptr;
     sv::Buddy pool;
     void *h_arena = nullptr;
+    char *d_arena = nullptr;  // the arena's device-visible address
     sv::Buddy arena;
     uint64_t items_cap = 0;        // work items a batch may hold
     uint64_t captures_at_create = 0;
@@ -166,6 +172,12 @@ uint32_t *dev_words(sieve_server *s, const Request *r)
     return wants_words(r) ? s->d_pool + r->dev_off / 4 : nullptr;
 }
 
+// The device-visible address of a request's block of the host arena.
+uint32_t *arena_words(sieve_server *s, const Request *r)
+{
+    return reinterpret_cast<uint32_t *>(s->d_arena + r->host_off);
+}
+
 // A request is finished: its device block goes back to the pool (its copy
 // to the host is complete); the host block stays until released.
 void finish_locked(sieve_server *s, Request *r)
@@ -198,24 +210,33 @@ void take_batch_locked(sieve_server *s, Lane &lane)
     }
 }
 
-// A batch of one goes through the plain range launch, which skips the batch
-// staging, upload and graph (the lowest latency when requests arrive one at
-// a time); the count is published to the lane's pinned word.  Returns
-// sv::kNotAsync when the range is not eligible (empty, or bucketed).
+// A small batch (up to kMaxPlainBatch requests) goes as plain range
+// launches, one per request, one after another on the lane's stream: no
+// batch staging and no graph, the lowest latency when requests arrive a few
+// at a time.  Each count is published to the request's pinned word of the
+// lane.  Returns sv::kNotAsync, enqueueing nothing, when a range is not
+// eligible (empty, or bucketed): the batch then takes the batch launch.
 int launch_single_lane(sieve_server *s, Lane &lane)
 {
     sieve_ctx *c = s->ctx;
-    Request *r = lane.reqs[0];
-    uint32_t *d = dev_words(s, r);
-    *lane.h_pub = kUnpublished;
-    r->t_launch = now_ns();
-    const int st = sv::range_async(c, r->lo, r->hi, d, lane.d_pub, lane.stream);
-    step(s, "range launch");
-    if (st != SIEVE_OK)
-        return st;
-    if (d)
-        SV_HIP_TRY(c, hipMemcpyAsync(r->host, d, r->n_words * 4, hipMemcpyDeviceToHost, lane.stream));
-    step(s, "bitmap copy");
+    if (lane.reqs.size() > kMaxPlainBatch)
+        return sv::kNotAsync;
+    for (const Request *r : lane.reqs)
+        if (!sv::range_async_ok(c, r->lo, r->hi))
+            return sv::kNotAsync;
+    for (size_t j = 0; j < lane.reqs.size(); ++j) {
+        Request *r = lane.reqs[j];
+        uint32_t *d = dev_words(s, r);
+        lane.h_pub[j] = kUnpublished;
+        r->t_launch = now_ns();
+        const int st = sv::range_async(c, r->lo, r->hi, d, lane.d_pub + j, lane.stream);
+        if (st != SIEVE_OK)
+            return st == sv::kNotAsync ? SIEVE_EDEVICE : st;  // checked eligible above
+        step(s, "range launch");
+        if (d)
+            SV_HIP_TRY(c, sv::launch_copy_words(d, arena_words(s, r), r->n_words, lane.stream));
+        step(s, "bitmap copy");
+    }
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
     step(s, "event");
     lane.single = true;
@@ -248,8 +269,7 @@ int launch_batch_lane(sieve_server *s, Lane &lane)
     step(s, "batch launch");
     for (const Request *r : lane.reqs)
         if (wants_words(r))
-            SV_HIP_TRY(c, hipMemcpyAsync(r->host, dev_words(s, r), r->n_words * 4, hipMemcpyDeviceToHost,
-                                         lane.stream));
+            SV_HIP_TRY(c, sv::launch_copy_words(dev_words(s, r), arena_words(s, r), r->n_words, lane.stream));
     step(s, "bitmap copies");
     SV_HIP_TRY(c, hipEventRecord(lane.copied, lane.stream));
     step(s, "event");
@@ -293,12 +313,14 @@ void dispatcher(sieve_server *s)
                 continue;
             std::lock_guard<std::mutex> g(s->m);
             if (lane.single) {
-                Request *r = lane.reqs[0];
-                const unsigned long long v = *lane.h_pub;
-                if (v == kUnpublished)
-                    r->status = SIEVE_EDEVICE;
-                r->pi = v + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
-                finish_locked(s, r);
+                for (size_t j = 0; j < lane.reqs.size(); ++j) {
+                    Request *r = lane.reqs[j];
+                    const unsigned long long v = lane.h_pub[j];
+                    if (v == kUnpublished)
+                        r->status = SIEVE_EDEVICE;
+                    r->pi = v + ((r->lo <= 2 && 2 < r->hi) ? 1 : 0);
+                    finish_locked(s, r);
+                }
             } else {
                 lane.eng.pending = false;
                 const unsigned long long *cnt = sv::counts_host(lane.eng);
@@ -350,22 +372,29 @@ void dispatcher(sieve_server *s)
                 const uint64_t t_call = now_ns();
                 s->n_steps = 0;
                 step(s, "start");
-                st = sv::kNotAsync;
-                if (lane.reqs.size() == 1)
-                    st = launch_single_lane(s, lane);
+                st = launch_single_lane(s, lane);
                 const bool single = st == SIEVE_OK;
                 if (st == sv::kNotAsync)
                     st = launch_batch_lane(s, lane);
                 const uint64_t call_ns = now_ns() - t_call;
+                ++lane.calls;
+                lane.t_launch = t_call;
                 std::lock_guard<std::mutex> g(s->m);
                 s->stats.max_launch_call_ns = std::max(s->stats.max_launch_call_ns, call_ns);
                 s->stats.slow_launch_calls += call_ns > 1000000 ? 1 : 0;
                 if (s->log_slow && call_ns > 1000000) {
-                    std::fprintf(stderr, "sieve server: launch call of %zu request(s) took %.3f ms:", lane.reqs.size(),
-                                 call_ns * 1e-6);
+                    std::fprintf(stderr, "sieve server: lane %d call %llu of %zu request(s) took %.3f ms:",
+                                 static_cast<int>(&lane - s->lanes.data()),
+                                 static_cast<unsigned long long>(lane.calls), lane.reqs.size(), call_ns * 1e-6);
                     for (int k = 1; k < s->n_steps; ++k)
                         std::fprintf(stderr, " %s %.3f", s->step_name[k],
                                      (s->step_ns[k] - s->step_ns[k - 1]) * 1e-6);
+                    // what the other lanes had in flight when this call began
+                    for (const Lane &o : s->lanes)
+                        if (&o != &lane && o.busy)
+                            std::fprintf(stderr, " | lane %d busy %s for %.3f ms (%zu requests)",
+                                         static_cast<int>(&o - s->lanes.data()), o.single ? "single" : "batch",
+                                         (t_call - o.t_launch) * 1e-6, o.reqs.size());
                     std::fprintf(stderr, "\n");
                 }
                 ++s->stats.batches;
@@ -479,9 +508,12 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
     }
     if (st == SIEVE_OK) {
         const uint64_t arena = s->arena.init(s->cfg.host_arena_bytes, max_block);
-        if (arena == 0 || hipHostMalloc(&s->h_arena, arena, hipHostMallocDefault) != hipSuccess) {
+        if (arena == 0 ||
+            hipHostMalloc(&s->h_arena, arena, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             s->h_arena = nullptr;
             st = SIEVE_ENOMEM;
+        } else if (hipHostGetDevicePointer(reinterpret_cast<void **>(&s->d_arena), s->h_arena, 0) != hipSuccess) {
+            st = SIEVE_EDEVICE;
         }
         // Copy device memory over the whole arena once, so that the first
         // bitmap copied into each of its blocks while serving does not pay
@@ -502,7 +534,8 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
             e = hipEventCreateWithFlags(&lane.copied, hipEventDisableTiming);
         void *pub = nullptr;
         if (e == hipSuccess)
-            e = hipHostMalloc(&pub, 64, hipHostMallocMapped | hipHostMallocCoherent);
+            e = hipHostMalloc(&pub, kMaxPlainBatch * sizeof(unsigned long long),
+                              hipHostMallocMapped | hipHostMallocCoherent);
         if (e == hipSuccess) {
             lane.h_pub = static_cast<volatile unsigned long long *>(pub);
             e = hipHostGetDevicePointer(reinterpret_cast<void **>(&lane.d_pub), pub, 0);
@@ -545,7 +578,9 @@ int sieve_server_create(int hip_device, const sieve_server_config *cfg, sieve_se
         if (st != SIEVE_OK)
             break;
         const uint64_t copy = std::min<uint64_t>({64ull << 20, s->pool.size(), s->arena.size()});
-        if (hipMemcpyAsync(s->h_arena, s->d_pool, copy, hipMemcpyDeviceToHost, lane.stream) != hipSuccess)
+        if ((plain ? hipMemcpyAsync(s->h_arena, s->d_pool, copy, hipMemcpyDeviceToHost, lane.stream)
+                   : sv::launch_copy_words(s->d_pool, reinterpret_cast<uint32_t *>(s->d_arena), copy / 4,
+                                           lane.stream)) != hipSuccess)
             st = SIEVE_EDEVICE;
         const uint64_t words_cap = s->pool.size() / 4;
         for (uint64_t n_words : {10000ull, 800000ull, 3000000ull, 8000000ull, 40000000ull}) {
