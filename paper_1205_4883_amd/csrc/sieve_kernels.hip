@@ -16,7 +16,9 @@
 //      and its word moves by 15p per mark: one LDS atomic OR and one add;
 //   3. sparse primes: one lane per prime walks the multiples p*m with m
 //      prime to 15 (a wheel of period 30, gaps 6,4,2,4,2,4,6,2), so 8 of
-//      every 15 odd multiples are visited.
+//      every 15 odd multiples are visited.  Those not carried from the
+//      previous segment are handed out 64 at a time to the wavefronts as
+//      they come free.
 // Then every thread counts the unmarked bits of its words (popcount plus a
 // wavefront shuffle reduction) and, for bitmap output, stores them to HBM.
 //
@@ -503,21 +505,6 @@ __device__ __forceinline__ void seg_dense(uint32_t *seg_lds, const SegGeom &g, c
     }
 }
 
-// 2b. sparse primes [i_begin, n_primes): one lane per prime, each start
-//     computed afresh for this segment.
-template <bool kSmall>
-__device__ __forceinline__ void seg_sparse(uint32_t *seg_lds, const SegGeom &g, const uint32_t *primes,
-                                           const double *inv, uint32_t i_begin, uint32_t n_primes)
-{
-    for (uint32_t i = i_begin + threadIdx.x; i < n_primes; i += blockDim.x) {
-        const uint32_t p = primes[i];
-        const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
-        uint32_t o = st.off;
-        uint32_t idx = wheel_start(p, o, st.m30);
-        (void)mark_wheel<kSmall>(seg_lds, g.lim_bits, p, o, idx);
-    }
-}
-
 // Whether every marking prime is below 2^24 (the largest is the last).
 __device__ __forceinline__ bool small_primes(const uint32_t *primes, uint32_t n_primes)
 {
@@ -603,21 +590,60 @@ __device__ void finish_launch(const RangeArgs &r, unsigned long long wg_count)
         *r.publish = total + r.publish_add;  // read after the stream (or the published word) says so
 }
 
+// 2b. sparse primes [i_begin, n_primes), one lane per prime, each start
+//     computed afresh for this segment, shared out among the wavefronts as
+//     they come free: a wave takes the next 64 primes (a lane each) from
+//     the workgroup's LDS counter `units` (zero when the segment's marking
+//     starts), so that waves whose other marking ended early take more.
+template <bool kSmall>
+__device__ __forceinline__ void seg_sparse_shared(uint32_t *seg, const SegGeom &g, const uint32_t *primes,
+                                                  const double *inv, uint32_t i_begin, uint32_t n_primes,
+                                                  uint32_t *units)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t n_units = n_primes > i_begin ? (n_primes - i_begin + 63) / 64 : 0;
+    if (n_units == 0)
+        return;
+    uint32_t w = 0;
+    if (lane == 0)
+        w = atomicAdd(units, 1u);
+    w = __builtin_amdgcn_readfirstlane(w);
+    while (w < n_units) {
+        // take the next unit now, so that the atomic's trip through the
+        // busy LDS queue overlaps this unit's marking
+        uint32_t next = 0;
+        if (lane == 0)
+            next = atomicAdd(units, 1u);
+        const uint32_t i = i_begin + w * 64 + lane;
+        if (i < n_primes) {
+            const uint32_t p = primes[i];
+            const Start st = first_multiple(g.n0, g.nf, p, inv[i], g.lim_bits);
+            uint32_t o = st.off;
+            uint32_t idx = wheel_start(p, o, st.m30);
+            (void)mark_wheel<kSmall>(seg, g.lim_bits, p, o, idx);
+        }
+        w = __builtin_amdgcn_readfirstlane(next);
+    }
+}
+
 // Sieve segment `seg` of one range into LDS and emit its words; returns the
 // number of primes among this thread's words.  tabs: the pre-sieve tables in
 // LDS; seg_lds: seg_words_max words of LDS, which the caller may reuse after
 // its next __syncthreads.  kSmall: every marking prime is below 2^24.
+// units: the workgroup's LDS counter for the shared sparse primes, zero
+// before the segment's first barrier (4096 seeded intervals in one batch:
+// 3.12 -> 3.09 ms against a fixed split).
 template <bool kWrite, bool kSmall>
 __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint32_t seg_words_max,
                                   uint64_t seg, uint64_t first_odd, uint64_t nbits, uint64_t n_words,
                                   const uint32_t *primes, const double *inv, uint32_t n_dense,
-                                  uint32_t n_primes, uint32_t *out)
+                                  uint32_t n_primes, uint32_t *out, uint32_t *units)
 {
     const SegGeom g = seg_geom(seg, seg_words_max, first_odd, n_words);
     seg_presieve<false>(tabs, seg_lds, g);
     __syncthreads();
     seg_dense(seg_lds, g, primes, inv, n_dense);
-    seg_sparse<kSmall>(seg_lds, g, primes, inv, n_dense, n_primes);
+    seg_sparse_shared<kSmall>(seg_lds, g, primes, inv, n_dense, n_primes, units);
     __syncthreads();
     return seg_count<kWrite>(seg_lds, g, first_odd, nbits, n_words, out);
 }
@@ -629,12 +655,19 @@ constexpr int kCarry = 4;
 constexpr uint32_t kCarryCap = 1u << 28;
 constexpr uint32_t kCarryNone = 0xffffffffu;
 
-// The sparse primes of one segment of a run: the first kCarry per lane
+// The sparse primes of one segment (of a run): the first kCarry per lane
 // continue from the multiple carried over from the previous segment (or
-// start afresh on the run's first segment, k == 0), the rest start afresh.
+// start afresh on a run's first segment, k == 0).  The rest start afresh,
+// shared out 64 at a time, a lane each, to the wavefronts as they come free
+// from the workgroup's LDS counter `units` (zero at the segment's start):
+// the waves whose fixed share (dense primes, carried primes) ends early
+// take more, so fewer wait at the marking barrier.  (Timed per wave, the
+// youngest waves of a workgroup, issued last, end their fixed share last;
+// [2, 1e10): 0.634 -> 0.623 ms.)
 template <bool kSmall>
 __device__ __forceinline__ void sparse_phase(uint32_t *seg, const SegGeom &g, const PrimeArgs &pa, uint32_t t,
-                                             uint32_t k, uint32_t carry_end, uint32_t (&carry)[kCarry])
+                                             uint32_t k, uint32_t carry_end, uint32_t (&carry)[kCarry],
+                                             uint32_t *units)
 {
 #pragma unroll
     for (int j = 0; j < kCarry; ++j) {
@@ -658,7 +691,7 @@ __device__ __forceinline__ void sparse_phase(uint32_t *seg, const SegGeom &g, co
         o = mark_wheel<kSmall>(seg, g.lim_bits, p, o, idx) - g.lim_bits;
         carry[j] = o < kCarryCap ? (idx << 29) | o : kCarryNone;
     }
-    seg_sparse<kSmall>(seg, g, pa.primes, pa.inv, carry_end, pa.n_primes);
+    seg_sparse_shared<kSmall>(seg, g, pa.primes, pa.inv, carry_end, pa.n_primes, units);
 }
 
 // Resident workgroups pop work items from the launch's work queues (zero at
@@ -678,6 +711,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 {
     __shared__ __align__(16) uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
+    __shared__ uint32_t units;
     __shared__ unsigned long long red[16];
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
@@ -704,13 +738,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             if (k)
                 __syncthreads();  // the previous segment's count has read the LDS
             const SegGeom g = seg_geom(first + k, seg_words, r.first_odd, r.n_words);
+            if (t == 0)
+                units = 0;  // no wave takes a unit before the barrier below
             seg_presieve<true>(tabs, seg, g);
             __syncthreads();
             seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense, count > 1);
             if (small)
-                sparse_phase<true>(seg, g, pa, t, k, carry_end, carry);
+                sparse_phase<true>(seg, g, pa, t, k, carry_end, carry, &units);
             else
-                sparse_phase<false>(seg, g, pa, t, k, carry_end, carry);
+                sparse_phase<false>(seg, g, pa, t, k, carry_end, carry, &units);
             if (r.buckets)
                 seg_buckets(seg, first + k, r.buckets, r.bucket_count, r.bucket_depth);
             __syncthreads();
@@ -735,6 +771,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 {
     __shared__ __align__(16) uint32_t lds[kTableWords + kSegMax];
     __shared__ uint32_t item_sh;
+    __shared__ uint32_t units;
     __shared__ uint32_t red[16];
     uint32_t *tabs = lds;
     uint32_t *seg = lds + kTableWords;
@@ -756,6 +793,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                 item_counts[prev] = total;
             }
             item_sh = next_item(counters, q, n_items, pass);
+            units = 0;  // every wave has left the previous item's marking
         }
         __syncthreads();
         const uint32_t item = item_sh;
@@ -767,10 +805,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
         uint32_t c;
         if (iv.word_offset != ~0ull)
             c = sieve_segment<true, kSmall>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
-                                    iv.n_dense, iv.n_primes, words + iv.word_offset);
+                                    iv.n_dense, iv.n_primes, words + iv.word_offset, &units);
         else
             c = sieve_segment<false, kSmall>(tabs, seg, seg_words, s, iv.first_odd, iv.nbits, iv.n_words, primes, inv,
-                                     iv.n_dense, iv.n_primes, nullptr);
+                                     iv.n_dense, iv.n_primes, nullptr, &units);
         c = wave_sum(c);
         if ((threadIdx.x & 63) == 0)
             red[threadIdx.x >> 6] = c;

@@ -102,6 +102,37 @@ def test_server_single_requests_take_the_plain_launch(sv, alone, oracle_mod):
         server.close()
 
 
+def test_server_small_batches_as_plain_launches(sv, alone, oracle_mod):
+    # A batch of two to eight requests goes as plain launches, one after
+    # another on the lane's stream, each count published to its own pinned
+    # word and each bitmap copied back by the copy kernel: submitted in
+    # groups of five to a one-lane server, the groups become such batches
+    # (the first request of a group may leave alone), and every result
+    # equals the oracle.
+    lo, hi, bm = _requests(51, 40, max_len=3e7)
+    server = sv.Server(0, lanes=1)
+    try:
+        ids, got = [], {}
+        print("case server small batches (8 groups of 5)", flush=True)
+        for g in range(0, 40, 5):
+            ids += [server.submit(int(lo[i]), int(hi[i]), bool(bm[i])) for i in range(g, g + 5)]
+            got.update(_drain(server, len(ids) - len(got)))
+        st = server.stats()
+        assert st["completed"] == 40 and st["graph_captures"] == 0
+        assert st["max_batch_seen"] >= 2, st
+        assert st["single_launches"] == st["batches"], st  # no batch graph was needed
+    finally:
+        server.close()
+    for i in range(40):
+        r = got[ids[i]]
+        assert r["status"] == 0
+        if bm[i]:
+            want, want_pi = oracle_mod.bitmap(int(lo[i]), int(hi[i]))
+            assert r["pi"] == want_pi and np.array_equal(r["words"], want), i
+        else:
+            assert r["pi"] == oracle_mod.count(int(lo[i]), int(hi[i])), i
+
+
 def test_server_budget_binds_device_memory(sv, alone):
     # The HBM budget is real memory: 64 MiB for the context, each lane's
     # batch buffers, and the rest as the device pool the admitted bitmaps
