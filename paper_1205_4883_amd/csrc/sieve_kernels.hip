@@ -473,20 +473,36 @@ __device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg
 //     start of prime r*64*nw + l*nw + w, so each wave gets an interleaved
 //     share of the primes; the wave then marks its (up to) 64 primes one
 //     after another.  The share is heaviest for wave 0 (the smallest prime
-//     of every group of nw).  reversed numbers the waves from the other end:
-//     inside a run of segments the carried sparse primes weigh most on the
-//     first waves (a wave's lanes hold consecutive primes, the smallest in
-//     wave 0), and giving those waves the lightest dense share evens out the
-//     work before the marking barrier (measured on [2, 1e10): 0.647 -> 0.636
-//     ms; single segments keep the plain order, where reversing cost up to
-//     6% at [2, 1e9)).
+//     of every group of nw).  The order depends on the work item:
+//     - kDensePlain (single segments): waves 0..nw-1 in order;
+//     - kDenseReversed (pairs of segments): numbered from the other end.
+//       The carried sparse primes weigh most on the first waves (a wave's
+//       lanes hold consecutive primes, the smallest in wave 0), so those
+//       waves get the lightest dense share ([2, 1e10) before the change
+//       below: 0.647 -> 0.636 ms; single segments lost up to 6%);
+//     - kDenseOldest (runs of three or more segments): only waves 0..7 take
+//       dense primes, two per SIMD, numbered from the other end.  Timed per
+//       wave, the waves a workgroup issues first run fastest, and waves
+//       8..15 then go straight to their carried and shared sparse primes
+//       ([2, 1e10): 0.620 -> 0.607 ms, 10^10 integers at 10^12: 1.589 ->
+//       1.574 ms; four, six, ten or twelve dense waves measured slower).
+enum DenseOrder : uint32_t { kDensePlain, kDenseReversed, kDenseOldest };
+constexpr uint32_t kDenseOldestWaves = 8;
+
 __device__ __forceinline__ void seg_dense(uint32_t *seg_lds, const SegGeom &g, const uint32_t *primes,
-                                          const double *inv, uint32_t n_dense, bool reversed = false)
+                                          const double *inv, uint32_t n_dense, DenseOrder order = kDensePlain)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t lane = t & 63;
-    const uint32_t nw = blockDim.x >> 6;
-    const uint32_t wave = reversed ? nw - 1 - (t >> 6) : t >> 6;
+    uint32_t nw = blockDim.x >> 6;
+    uint32_t wave = t >> 6;
+    if (order == kDenseOldest && nw >= kDenseOldestWaves) {
+        if (wave >= kDenseOldestWaves)
+            return;
+        nw = kDenseOldestWaves;
+    }
+    if (order != kDensePlain)
+        wave = nw - 1 - wave;
     for (uint32_t r0 = 0; r0 + wave < n_dense; r0 += 64 * nw) {
         const uint32_t i = r0 + lane * nw + wave;
         uint32_t p = 0, s0 = 0, m30 = 0, u = 1;
@@ -742,7 +758,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
                 units = 0;  // no wave takes a unit before the barrier below
             seg_presieve<true>(tabs, seg, g);
             __syncthreads();
-            seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense, count > 1);
+            seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense,
+                      count > 2 ? kDenseOldest : count > 1 ? kDenseReversed : kDensePlain);
             if (small)
                 sparse_phase<true>(seg, g, pa, t, k, carry_end, carry, &units);
             else
