@@ -803,7 +803,7 @@ int engine_stage(sieve_ctx *c, BatchEngine &e, const sieve_interval *iv, uint32_
     HIP_TRY(c, hipSetDevice(c->device));
     if (int st = ensure_primes(c, max_bound))
         return st;
-    // The staging buffers may still feed the previous launch's uploads.
+    // The staging buffers may still be read by the previous launch's stage kernel.
     if (e.pending)
         HIP_TRY(c, hipEventSynchronize(e.done));
     e.pending = false;

@@ -76,7 +76,7 @@ struct PrimeArgs {
     uint32_t n_primes;  // primes[0, n_primes) are used
 };
 
-// One interval of a batch, as uploaded to the device.
+// One interval of a batch, as staged for the device.
 struct BatchInterval {
     uint64_t first_odd;
     uint64_t nbits;
@@ -88,12 +88,12 @@ struct BatchInterval {
     uint32_t pad;
 };
 
-// Sizes of a batch launch, in device memory.  The header
-// starts one upload blob: the interval table sits at byte iv_off and the work
-// list (interval index of each item) at item_off, so one copy moves a batch.
-// The blob's second part, kCounterWords words at byte kBlobAlign, holds the
-// batch's work queues (zeroed by the reset kernel; the count lines are
-// unused).
+// Sizes of a batch launch, in device memory.  The header starts one blob,
+// staged in pinned host memory and copied to the device by the batch's stage
+// kernel: the interval table sits at byte iv_off and the work list (interval
+// index of each item) at item_off.  The blob's second part, kCounterWords
+// words at byte kBlobAlign, holds the batch's work queues (zeroed by the
+// stage kernel; the count lines are unused).
 struct BatchHeader {
     uint32_t n_intervals;
     uint32_t n_items;
