@@ -474,12 +474,14 @@ __device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg
 //     share of the primes; the wave then marks its (up to) 64 primes one
 //     after another.  The share is heaviest for wave 0 (the smallest prime
 //     of every group of nw).  The order depends on the work item:
-//     - kDensePlain (single segments): waves 0..nw-1 in order;
-//     - kDenseReversed (pairs of segments): numbered from the other end.
-//       The carried sparse primes weigh most on the first waves (a wave's
-//       lanes hold consecutive primes, the smallest in wave 0), so those
-//       waves get the lightest dense share ([2, 1e10) before the change
-//       below: 0.647 -> 0.636 ms; single segments lost up to 6%);
+//     - kDensePlain (single segments of a range): waves 0..nw-1 in order;
+//     - kDenseReversed (pairs of segments, and batch items): numbered from
+//       the other end.  The carried sparse primes weigh most on the first
+//       waves (a wave's lanes hold consecutive primes, the smallest in wave
+//       0), so those waves get the lightest dense share ([2, 1e10) before
+//       the change below: 0.647 -> 0.636 ms; single segments of a range lost
+//       up to 6%; the 4096-interval batch, whose sparse primes are all
+//       shared: 3.094 -> 3.065 ms);
 //     - kDenseOldest (runs of three or more segments): only waves 0..7 take
 //       dense primes, two per SIMD, numbered from the other end.  Timed per
 //       wave, the waves a workgroup issues first run fastest, and waves
@@ -658,7 +660,7 @@ __device__ uint32_t sieve_segment(const uint32_t *tabs, uint32_t *seg_lds, uint3
     const SegGeom g = seg_geom(seg, seg_words_max, first_odd, n_words);
     seg_presieve<false>(tabs, seg_lds, g);
     __syncthreads();
-    seg_dense(seg_lds, g, primes, inv, n_dense);
+    seg_dense(seg_lds, g, primes, inv, n_dense, kDenseReversed);
     seg_sparse_shared<kSmall>(seg_lds, g, primes, inv, n_dense, n_primes, units);
     __syncthreads();
     return seg_count<kWrite>(seg_lds, g, first_odd, nbits, n_words, out);
