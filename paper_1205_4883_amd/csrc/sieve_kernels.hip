@@ -835,8 +835,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
     }
 }
 
-// Zero a batch's work queues (a kernel, not a memset, so that it can sit in a
-// captured graph).
 // Copies a batch's blob (header, work queues, interval table, work list)
 // from the pinned host staging into device memory, with the work-queue
 // counters cleared, so that a batch launch is kernels only: no upload on a
