@@ -162,6 +162,10 @@ def test_tuning_sweep(gpu, oracle_mod, seg_bits, dense_limit, threads):
     (10**9 + 3, 10**9 + 2 * 10**8, 4096, 512, 0),
     (0, 3 * 10**8, 16384, 1024, 37),          # no dense primes: every prime carried or scanned
     (10**12 + 1, 10**12 + 4 * 10**8, 8192, 256, 0),  # runs inside bucket windows
+    # 16 waves: inside runs only waves 0..7 take dense primes, and the
+    # uncarried sparse primes are shared out from the LDS counter
+    (10**9 + 3, 10**9 + 3 * 10**8 + 7, 16384, 1024, 0),
+    (3 * 10**10, 3 * 10**10 + 3 * 10**8, 16384, 1024, 600),
 ])
 def test_runs_of_segments_with_carried_offsets(gpu, oracle_mod, sv_mod, lo, hi, seg_bits, threads,
                                                dense_limit):
