@@ -92,9 +92,10 @@ struct sieve_server {
     // SIEVE_SERVE_LOG_SLOW set in the environment, a call over 1 ms prints
     // how long each of its steps took.
     bool log_slow = false;
+    static constexpr int kMaxSteps = 24;  // a call of eight plain launches takes 18
     int n_steps = 0;
-    const char *step_name[8] = {};
-    uint64_t step_ns[8] = {};
+    const char *step_name[kMaxSteps] = {};
+    uint64_t step_ns[kMaxSteps] = {};
 
     std::mutex m;
     std::condition_variable cv_work;  // dispatcher: new submissions or stop
@@ -114,7 +115,7 @@ namespace {
 
 void step(sieve_server *s, const char *name)
 {
-    if (s->n_steps < 8) {
+    if (s->n_steps < sieve_server::kMaxSteps) {
         s->step_name[s->n_steps] = name;
         s->step_ns[s->n_steps++] = now_ns();
     }
