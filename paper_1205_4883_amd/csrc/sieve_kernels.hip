@@ -837,9 +837,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
 
 // Copies a batch's blob (header, work queues, interval table, work list)
 // from the pinned host staging into device memory, with the work-queue
-// counters cleared, so that a batch launch is kernels only: no upload on a
-// copy engine.  The length is the header's blob_chunks, read once per
-// wavefront from the host copy.
+// counters cleared, so that a batch launch is kernels only: no runtime copy
+// call (hipMemcpyAsync or a graph memcpy node).  The length is the header's
+// blob_chunks, read once per wavefront from the host copy.
 __global__ void __launch_bounds__(256) batch_stage_kernel(const uint4 *src, uint4 *dst)
 {
     const uint32_t n = __builtin_amdgcn_readfirstlane(reinterpret_cast<const BatchHeader *>(src)->blob_chunks);
@@ -875,8 +875,8 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchHeader *hd
 // dst[0, n_words) = src[0, n_words), 16 bytes per thread and step, four
 // loads in flight per thread (both 16-byte aligned).  The server returns
 // bitmaps with it into its pinned host arena, mapped into the device, so
-// that a copy runs on the lane's compute queue in stream order instead of on
-// a copy engine.
+// that a copy is a kernel launch of its own in stream order on the lane
+// instead of a runtime copy call (hipMemcpyAsync).
 __global__ void __launch_bounds__(256) copy_words_kernel(const uint4 *src, uint4 *dst, uint64_t n_words)
 {
     constexpr int kU = 4;
@@ -1349,7 +1349,7 @@ hipError_t launch_copy_words(const uint32_t *src, uint32_t *dst, uint64_t n_word
         return hipSuccess;
     // 16 workgroups with four loads in flight per thread already reach the
     // PCIe rate to host memory (measured 52-56 GB/s for 8-64 MiB, as fast as
-    // a copy-engine copy); more would only hold CU slots (a CU running a
+    // hipMemcpyAsync); more would only hold CU slots (a CU running a
     // sieve launch's two workgroups has none free) that concurrent sieve
     // launches need.
     const uint64_t n16 = (n_words + 3) / 4;
