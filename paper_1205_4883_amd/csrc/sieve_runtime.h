@@ -93,10 +93,11 @@ struct sieve_ctx {
     double *d_inv = nullptr;  // d_inv[i] = 1 / d_primes[i]
 
     // Per-call device counters (work queues and partial counts, kCounterWords
-    // words each): kSlots slots used in turn, each guarded by an event so
-    // that an asynchronous call still running on another stream never sees
-    // its slot reset.
-    static constexpr int kSlots = 16;
+    // words each): kSlots slots, the first free one in turn, each guarded by
+    // an event so that an asynchronous call still running on another stream
+    // never sees its slot reset.  32 covers a server's three lanes with eight
+    // plain launches each in flight, so the dispatcher does not wait for one.
+    static constexpr int kSlots = 32;
     uint32_t *d_ctr = nullptr;  // kSlots * kCounterWords words
     hipEvent_t slot_done[kSlots] = {};
     bool slot_used[kSlots] = {};
