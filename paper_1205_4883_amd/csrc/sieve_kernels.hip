@@ -482,12 +482,14 @@ __device__ __forceinline__ void seg_presieve(const uint32_t *tabs, uint32_t *seg
 //       the change below: 0.647 -> 0.636 ms; single segments of a range lost
 //       up to 6%; the 4096-interval batch, whose sparse primes are all
 //       shared: 3.094 -> 3.065 ms);
-//     - kDenseOldest (runs of three or more segments): only waves 0..7 take
-//       dense primes, two per SIMD, numbered from the other end.  Timed per
-//       wave, the waves a workgroup issues first run fastest, and waves
-//       8..15 then go straight to their carried and shared sparse primes
-//       ([2, 1e10): 0.620 -> 0.607 ms, 10^10 integers at 10^12: 1.589 ->
-//       1.574 ms; four, six, ten or twelve dense waves measured slower).
+//     - kDenseOldest (runs of three or more segments without hit buckets):
+//       only waves 0..7 take dense primes, two per SIMD, numbered from the
+//       other end.  Timed per wave, the waves a workgroup issues first run
+//       fastest, and waves 8..15 then go straight to their carried and
+//       shared sparse primes ([2, 1e10): 0.620 -> 0.607 ms, 10^10 integers
+//       at 10^12: 1.589 -> 1.574 ms; four, six, ten or twelve dense waves
+//       measured slower).  With hit buckets the reversed order is kept
+//       (10^10 integers at 10^13: 2.53 -> 2.47 ms against this order).
 enum DenseOrder : uint32_t { kDensePlain, kDenseReversed, kDenseOldest };
 constexpr uint32_t kDenseOldestWaves = 8;
 
@@ -761,7 +763,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)
             seg_presieve<true>(tabs, seg, g);
             __syncthreads();
             seg_dense(seg, g, pa.primes, pa.inv, pa.n_dense,
-                      count > 2 ? kDenseOldest : count > 1 ? kDenseReversed : kDensePlain);
+                      count > 2 && !r.buckets ? kDenseOldest : count > 1 ? kDenseReversed : kDensePlain);
             if (small)
                 sparse_phase<true>(seg, g, pa, t, k, carry_end, carry, &units);
             else
